@@ -1,0 +1,182 @@
+/*
+ * sr.h -- C ABI of libsr, the MI355X (gfx950) short-range particle-particle
+ * force of the HACC hybrid N-body method (Habib et al., "HACC: Simulating Sky
+ * Surveys on State-of-the-Art Supercomputing Architectures", arXiv:1410.2805).
+ *
+ * What is computed
+ *   For every target particle i that is not passive,
+ *
+ *     a_i = sum_{j != i, s_ij < r_max^2}  m_j f_SR(s_ij) d_ij,
+ *     f_SR(s) = (s + eps)^(-3/2) - p(s),   p(s) = sum_{k=0..5} c_k s^k,
+ *
+ *   d_ij = x_j - x_i (minimum image in a periodic box), s_ij = d_ij . d_ij:
+ *   Eq. (force) of Sec. 3.1, with p the fifth-order polynomial that stands
+ *   in for the filtered grid force of Sec. 2.4 (Eq. (fitform)), eps the
+ *   Plummer softening added to s, G = 1 and lengths in grid units (Sec. 2.6).
+ *   Pairs are found through a chaining mesh of cells at least as wide as the
+ *   cutoff, searched over each cell and its 26 neighbours (Sec. 2.4, last
+ *   paragraph; Sec. 3.1, fixed bins of the short-range scale).  Passive
+ *   particles of a non-periodic (overloaded) domain -- those closer than the
+ *   skin width to a face -- receive no short-range force but act as sources
+ *   (Sec. 2.2).
+ *
+ * Conventions (all entry points)
+ *   - Particle data are float32 structure-of-arrays in DEVICE memory owned by
+ *     the caller: x[n], y[n], z[n], mass[n]; outputs likewise.  The library
+ *     never frees caller memory.  Coordinates must satisfy 0 <= x < L.
+ *   - Scratch memory comes from the context's arena (a single device
+ *     allocation, reused by every call; see sr_ctx_create).
+ *   - Every call only enqueues work on the context's HIP stream and returns;
+ *     it never waits for the device.  sr_sync waits and reports errors that
+ *     the device detected (SR_ERANGE for a coordinate outside [0, L) or NaN).
+ *   - Argument errors are reported synchronously by a negative return value;
+ *     sr_last_error gives a message.  Nothing is enqueued in that case.
+ *   - Output sizes are fixed by (box, cell, n) and can be computed on the host
+ *     with sr_grid_dims.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef SR_H
+#define SR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SR_OK = 0,
+    SR_EDEVICE = -5,  /* HIP runtime error */
+    SR_ENOMEM = -12,  /* scratch arena too small (fixed-size arena) or allocation failed */
+    SR_EBUSY = -16,   /* serving: no free slot / HBM budget exhausted */
+    SR_EINVAL = -22,  /* invalid argument */
+    SR_ERANGE = -34   /* device-detected: coordinate outside [0, L) or NaN */
+};
+
+/* Box [0, len[0]) x [0, len[1]) x [0, len[2]).
+ *   periodic != 0 : periodic in all three axes, minimum-image separations.
+ *   periodic == 0 : open domain of an overloaded node (Sec. 2.2); particles
+ *                   whose distance to the nearest face is < skin (strictly,
+ *                   FP64) are passive.  skin is ignored when periodic. */
+typedef struct sr_box {
+    double len[3];
+    int32_t periodic;
+    int32_t _pad;
+    double skin;
+} sr_box;
+
+typedef struct sr_ctx sr_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).
+ *   arena_bytes > 0 : fixed scratch arena of that many bytes, allocated
+ *                     here; calls needing more return SR_ENOMEM.
+ *   arena_bytes == 0: the arena grows on demand.  The first call that
+ *                     needs more waits for the stream, frees the old arena
+ *                     and allocates 1.25x the need (a pool in the spirit of
+ *                     the Bigchunk allocator of Sec. 2.7).
+ * On success *out receives the context.  Returns SR_EINVAL / SR_EDEVICE /
+ * SR_ENOMEM. */
+int sr_ctx_create(int device, void *hip_stream, size_t arena_bytes, sr_ctx **out);
+
+/* Wait for the context's stream, free the arena and the context. */
+int sr_ctx_destroy(sr_ctx *ctx);
+
+/* Message of the last error returned on this context ("" if none).  The
+ * string is owned by the context and valid until its next call. */
+const char *sr_last_error(const sr_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+int sr_set_stream(sr_ctx *ctx, void *hip_stream);
+
+/* Bytes of arena currently allocated, and the high-water need so far. */
+int sr_arena_info(const sr_ctx *ctx, size_t *allocated, size_t *high_water);
+
+/* Wait for all work enqueued by this context; returns SR_ERANGE if a kernel
+ * saw a coordinate outside [0, L) or a NaN since the last sr_sync (the
+ * results of such calls are undefined but every access stayed in bounds),
+ * SR_EDEVICE on a HIP error, else SR_OK.  Clears the device status. */
+int sr_sync(sr_ctx *ctx);
+
+/* Chaining-mesh geometry (host only, no device work): dims[d] =
+ * floor(len[d] / cell) cells per axis, *n_cells = their product.  Cell
+ * width cs_d = len[d] / dims[d] >= cell.  SR_EINVAL if cell <= 0, a side
+ * is not positive, or a count overflows int32. */
+int sr_grid_dims(const sr_box *box, double cell, int32_t dims[3], int64_t *n_cells);
+
+/* Scratch bytes sr_force (with_force = 1) or sr_bin (0) needs for n
+ * particles in this geometry; a fixed arena of at least this size never
+ * returns SR_ENOMEM for such a call. */
+int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force, size_t *bytes);
+
+/* Chaining-mesh binning (a stable counting sort by cell).
+ *   x, y, z      : device float32[n], 0 <= coordinate < len.
+ *   n            : 0 <= n <= 2^31 - 1.
+ *   cell         : requested cell width (see sr_grid_dims).
+ *   cell_offsets : device int32[n_cells + 1]; particles of cell c occupy
+ *                  sorted slots [cell_offsets[c], cell_offsets[c+1]).
+ *                  Cell of a coordinate: floor(x * (dims/len)) evaluated in
+ *                  FP64 and clamped to dims-1; cell id = cx + dims[0]*(cy +
+ *                  dims[1]*cz).
+ *   perm         : device int32[n]; perm[k] = original index of sorted slot
+ *                  k.  Within a cell, original order is kept (stable), so
+ *                  the result is unique and deterministic.
+ * This is the permutation array of Sec. 2.7 over the fixed short-range bins
+ * of Sec. 3.1.  Errors: SR_EINVAL (null pointer with n > 0, bad geometry,
+ * n out of range), SR_ENOMEM; SR_ERANGE later from sr_sync. */
+int sr_bin(sr_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
+           const sr_box *box, double cell, int32_t *cell_offsets, int32_t *perm);
+
+/* Short-range accelerations (Eq. (force), Sec. 3.1) of all n particles.
+ *   x, y, z, mass : device float32[n] (mass may be any finite values).
+ *   cell          : chaining-mesh cell width; needs cs_d >= r_max and, in a
+ *                   periodic box, dims[d] >= 3 and 2 r_max < len[d].
+ *   r_max, eps    : cutoff radius (> 0) and softening (1e-20 <= eps), eps
+ *                   added to s as in Eq. (force).
+ *   poly          : HOST float[6], c_0..c_5 of p(s), read during the call.
+ *   ax, ay, az    : device float32[n] outputs in the caller's original
+ *                   particle order; passive particles get exactly 0.
+ *   momentum3     : optional device double[3]; receives sum_i m_i a_i,
+ *                   reduced in FP64 on the device in a fixed order (a Newton's
+ *                   third law check; ~0 in a periodic box).
+ * Arithmetic is float32 (one reciprocal square root per pair); each
+ * target's sum is formed in tiles of at most 256 sources whose partial sums
+ * are then added, and the result is deterministic (no floating-point atomics,
+ * fixed order).  Errors: SR_EINVAL, SR_ENOMEM synchronously; SR_ERANGE from
+ * sr_sync. */
+int sr_force(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
+             int64_t n, const sr_box *box, double cell, float r_max, float eps,
+             const float poly[6], float *ax, float *ay, float *az, double *momentum3);
+
+/* Pair statistics for the same call shape as sr_force (no accelerations):
+ *   *useful     : directed pairs (i, j), i != j, i not passive, with the
+ *                 float32 s_ij < r_max^2 -- the interactions Eq. (force)
+ *                 requires.
+ *   *candidates : directed pairs the chaining mesh presents to the force
+ *                 loop: sum over non-passive targets of the particle count
+ *                 of their 27 neighbour cells.
+ *   per_target  : optional device int32[n]: useful partners of each particle
+ *                 (original order).
+ * *useful and *candidates are HOST pointers; this call waits for the
+ * stream (it is a measurement helper, not part of the timed path). */
+int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
+                  const sr_box *box, double cell, float r_max, int32_t *per_target,
+                  int64_t *useful, int64_t *candidates);
+
+/* Device-side timing of sr_force (a measurement helper).  While enabled,
+ * each sr_force call records HIP events on the context's stream: one before
+ * its preparation (binning, gather, work items), one before the pair-loop
+ * kernel and one after it. */
+int sr_timing_enable(sr_ctx *ctx, int enable);
+
+/* Waits for the stream and returns, summed over the sr_force calls recorded
+ * since the previous collect, the milliseconds of the preparation phase and
+ * of the pair-loop kernel, and the number of calls (HOST pointers; any may
+ * be NULL).  Resets the record. */
+int sr_timing_collect(sr_ctx *ctx, double *prep_ms, double *force_ms, int64_t *calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SR_H */

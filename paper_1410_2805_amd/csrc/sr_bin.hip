@@ -1,0 +1,470 @@
+// Chaining-mesh binning on gfx950: cell ids, histogram, exclusive scan,
+// scatter and a per-cell ascending sort of original indices.  The result is
+// the stable counting sort of the particles by cell (Sec. 2.4 chaining mesh;
+// Sec. 2.7 permutation array; Sec. 3.1 fixed bins of the short-range scale).
+//
+//   k_cellid   cell of each particle in FP64, histogram by atomic increment
+//              (the returned old count is an arrival rank, unordered)
+//   scan       three-phase exclusive prefix sum with wavefront scans
+//   k_scatter  perm[offsets[cell] + rank] = i (grouped by cell, unordered
+//              inside a cell)
+//   k_segsort  restores stability: the slots of one cell hold that cell's
+//              original indices, so sorting them ascending is exactly the
+//              stable order.  One wavefront per cell: registers (<= 64),
+//              wavefront-private LDS bitonic sort (<= 1024); larger cells go
+//              to k_segsort_large (one block, LDS-sorted runs merged by rank).
+//              The same pass gathers the sorted float4 (x, y, z, m) copy and
+//              counts force work items per cell.
+#include <climits>
+
+#include "sr_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;  // 4096 entries per scan tile
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_inclusive_scan(int v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(v, d, 64);
+        if (lane >= d)
+            v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over a 256-thread block; *total receives the block sum.
+__device__ int block_exclusive_scan(int v, int *sh /*[5]*/, int *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = wave_inclusive_scan(v, lane);
+    if (lane == 63)
+        sh[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            int t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[kBlock / 64] = run;
+    }
+    __syncthreads();
+    int r = inc - v + sh[wid];
+    *total = sh[kBlock / 64];
+    __syncthreads();
+    return r;
+}
+
+__global__ void k_fill(int *__restrict__ p, int value, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = value;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cellid(const float *__restrict__ x,
+                                                   const float *__restrict__ y,
+                                                   const float *__restrict__ z, int n, Geom g,
+                                                   int *__restrict__ cid, int *__restrict__ slot,
+                                                   int *__restrict__ count, int *__restrict__ status)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const float p[3] = {x[i], y[i], z[i]};
+    int c[3];
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double v = (double)p[d];
+        if (!(v >= 0.0 && v < g.len[d])) {  // also catches NaN
+            bad = true;
+            c[d] = 0;
+        } else {
+            double t = floor(v * g.inv[d]);
+            int ci = (int)t;
+            c[d] = ci < g.nc[d] - 1 ? ci : g.nc[d] - 1;
+        }
+    }
+    if (bad)
+        atomicOr(status, 1);
+    int id = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+    cid[i] = id;
+    slot[i] = atomicAdd(&count[id], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int *__restrict__ in, int m,
+                                                        int *__restrict__ part)
+{
+    __shared__ int sh[8];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        s += (base + k < m) ? in[base + k] : 0;
+    int total;
+    (void)block_exclusive_scan(s, sh, &total);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the tile partials in place.
+__global__ __launch_bounds__(kBlock) void k_scan_partials(int *__restrict__ part, int ntiles)
+{
+    __shared__ int sh[8];
+    int carry = 0;
+    for (int b = 0; b < ntiles; b += kBlock) {
+        int i = b + threadIdx.x;
+        int v = i < ntiles ? part[i] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, sh, &total);
+        if (i < ntiles)
+            part[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int *__restrict__ in, int m,
+                                                      const int *__restrict__ part,
+                                                      int *__restrict__ out)
+{
+    __shared__ int sh[8];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < m) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_exclusive_scan(s, sh, &total) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m)
+            out[base + k] = run;
+        run += v[k];
+        if (base + k == m - 1)
+            out[m] = run;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int *__restrict__ cid,
+                                                    const int *__restrict__ slot, int n,
+                                                    const int *__restrict__ offsets,
+                                                    int *__restrict__ perm)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        perm[offsets[cid[i]] + slot[i]] = i;
+}
+
+__device__ __forceinline__ int bitonic64(int v, int lane)
+{
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            int o = __shfl_xor(v, j, 64);
+            bool up = (lane & k) == 0;
+            bool lower = (lane & j) == 0;
+            int mn = v < o ? v : o;
+            int mx = v < o ? o : v;
+            v = (lower == up) ? mn : mx;
+        }
+    }
+    return v;
+}
+
+// Bitonic sort of P (power of two, <= 1024) ints in LDS by one wavefront.
+__device__ void lds_bitonic(int *buf, int P, int lane)
+{
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < P / 2; t += 64) {
+                int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                int l = i + j;
+                bool up = (i & k) == 0;
+                int a = buf[i], c = buf[l];
+                if ((a > c) == up) {
+                    buf[i] = c;
+                    buf[l] = a;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+__device__ __forceinline__ void gather_one(float4 *sorted, int k, int src, const float *x,
+                                           const float *y, const float *z, const float *m)
+{
+    sorted[k] = make_float4(x[src], y[src], z[src], m[src]);
+}
+
+// One wavefront per cell.
+__global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offsets, int ncell,
+                                                    int *__restrict__ perm,
+                                                    int *__restrict__ large_list,
+                                                    int *__restrict__ large_count,
+                                                    const float *__restrict__ x,
+                                                    const float *__restrict__ y,
+                                                    const float *__restrict__ z,
+                                                    const float *__restrict__ m,
+                                                    float4 *__restrict__ sorted,
+                                                    int *__restrict__ chunk_count)
+{
+    __shared__ int buf[kBlock / 64][kLargeCell];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int cell = blockIdx.x * (kBlock / 64) + wid;
+    if (cell >= ncell)
+        return;
+    const int b = offsets[cell];
+    const int len = offsets[cell + 1] - b;
+    if (chunk_count && lane == 0)
+        chunk_count[cell] = (len + kChunk - 1) / kChunk;
+    if (len <= 64) {
+        int v = lane < len ? perm[b + lane] : INT_MAX;
+        v = bitonic64(v, lane);
+        if (lane < len) {
+            perm[b + lane] = v;
+            if (sorted)
+                gather_one(sorted, b + lane, v, x, y, z, m);
+        }
+    } else if (len <= kLargeCell) {
+        int P = 128;
+        while (P < len)
+            P <<= 1;
+        int *sb = buf[wid];
+        for (int t = lane; t < P; t += 64)
+            sb[t] = t < len ? perm[b + t] : INT_MAX;
+        wave_sync();
+        lds_bitonic(sb, P, lane);
+        for (int t = lane; t < len; t += 64) {
+            int v = sb[t];
+            perm[b + t] = v;
+            if (sorted)
+                gather_one(sorted, b + t, v, x, y, z, m);
+        }
+    } else if (lane == 0) {
+        int k = atomicAdd(large_count, 1);
+        large_list[k] = cell;
+    }
+}
+
+// Block-level sort of one large cell: LDS-sorted runs of kLargeCell, then
+// merge rounds in which every element finds its output slot from its rank in
+// the partner run (values are distinct original indices).
+__global__ __launch_bounds__(kBlock) void k_segsort_large(const int *__restrict__ offsets,
+                                                          int *__restrict__ perm,
+                                                          int *__restrict__ tmp,
+                                                          const int *__restrict__ large_list,
+                                                          const int *__restrict__ large_count,
+                                                          const float *__restrict__ x,
+                                                          const float *__restrict__ y,
+                                                          const float *__restrict__ z,
+                                                          const float *__restrict__ m,
+                                                          float4 *__restrict__ sorted)
+{
+    __shared__ int buf[kLargeCell];
+    const int nl = *large_count;
+    for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+        const int cell = large_list[li];
+        const int b = offsets[cell];
+        const int len = offsets[cell + 1] - b;
+        // 1) sort runs of kLargeCell in LDS (bitonic, whole block)
+        for (int r0 = 0; r0 < len; r0 += kLargeCell) {
+            int rl = len - r0 < kLargeCell ? len - r0 : kLargeCell;
+            for (int t = threadIdx.x; t < kLargeCell; t += kBlock)
+                buf[t] = t < rl ? perm[b + r0 + t] : INT_MAX;
+            __syncthreads();
+            for (int k = 2; k <= kLargeCell; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int t = threadIdx.x; t < kLargeCell / 2; t += kBlock) {
+                        int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                        int l = i + j;
+                        bool up = (i & k) == 0;
+                        int a = buf[i], c = buf[l];
+                        if ((a > c) == up) {
+                            buf[i] = c;
+                            buf[l] = a;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int t = threadIdx.x; t < rl; t += kBlock)
+                perm[b + r0 + t] = buf[t];
+            __syncthreads();
+        }
+        // 2) merge rounds, perm <-> tmp
+        int *src = perm + b;
+        int *dst = tmp + b;
+        for (int w = kLargeCell; w < len; w <<= 1) {
+            for (int e = threadIdx.x; e < len; e += kBlock) {
+                int pair0 = (e / (2 * w)) * (2 * w);
+                int mid = pair0 + w;              // start of the right run
+                int end = pair0 + 2 * w < len ? pair0 + 2 * w : len;
+                int v = src[e];
+                int lo, hi;
+                if (e < mid) {  // left element: count right elements < v
+                    lo = mid;
+                    hi = end;
+                } else {        // right element: count left elements < v
+                    lo = pair0;
+                    hi = mid;
+                }
+                int a = lo, c = hi;
+                while (a < c) {
+                    int h = (a + c) >> 1;
+                    if (src[h] < v)
+                        a = h + 1;
+                    else
+                        c = h;
+                }
+                int rank_other = a - lo;
+                int own = (e < mid) ? e - pair0 : e - mid;
+                dst[pair0 + own + rank_other] = v;
+            }
+            __syncthreads();
+            int *t = src;
+            src = dst;
+            dst = t;
+        }
+        if (src != perm + b) {
+            for (int e = threadIdx.x; e < len; e += kBlock)
+                perm[b + e] = src[e];
+            __syncthreads();
+        }
+        if (sorted) {
+            for (int e = threadIdx.x; e < len; e += kBlock)
+                gather_one(sorted, b + e, perm[b + e], x, y, z, m);
+        }
+        __syncthreads();
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int per)
+{
+    return (unsigned)((n + per - 1) / per);
+}
+
+}  // namespace
+
+int fill_enqueue(sr_ctx *ctx, int *p, int value, int64_t count)
+{
+    if (count <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, ctx->stream, p,
+                       value, count);
+    return sr_check_launch(ctx, "k_fill");
+}
+
+void scan_layout(Bump &b, int m, int **part)
+{
+    int tiles = (m + kScanTile - 1) / kScanTile;
+    *part = b.take<int>(tiles > 0 ? tiles : 1);
+}
+
+// out[0..m] = exclusive prefix sums of in[0..m-1], out[m] = total.
+int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out)
+{
+    if (m <= 0)
+        return fill_enqueue(ctx, out, 0, 1);
+    int tiles = (m + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(kBlock), 0, ctx->stream, in, m, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, ctx->stream, part, tiles);
+    hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(kBlock), 0, ctx->stream, in, m, part, out);
+    return sr_check_launch(ctx, "scan");
+}
+
+void bin_layout(Bump &b, int64_t n, const Geom &g, BinScratch &s)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    s.cid = b.take<int>(nn);
+    s.slot = b.take<int>(nn);
+    s.count = b.take<int>((size_t)g.ncell);
+    scan_layout(b, g.ncell, &s.scan_part);
+    s.tmp = b.take<int>(nn);
+    s.large_list = b.take<int>(nn / (kLargeCell + 1) + 1);
+    s.large_count = b.take<int>(1);
+}
+
+// Enqueue the whole binning pass.  sorted/m and chunk_count may be NULL.
+int bin_enqueue(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *m,
+                int n, const Geom &g, const BinScratch &s, int *offsets, int *perm,
+                float4 *sorted, int *chunk_count)
+{
+    int rc;
+    if ((rc = fill_enqueue(ctx, s.count, 0, g.ncell)))
+        return rc;
+    if ((rc = fill_enqueue(ctx, s.large_count, 0, 1)))
+        return rc;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_cellid, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
+                           x, y, z, n, g, s.cid, s.slot, s.count, ctx->status);
+        if ((rc = sr_check_launch(ctx, "k_cellid")))
+            return rc;
+    }
+    if ((rc = scan_enqueue(ctx, s.count, g.ncell, s.scan_part, offsets)))
+        return rc;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
+                           s.cid, s.slot, n, offsets, perm);
+        if ((rc = sr_check_launch(ctx, "k_scatter")))
+            return rc;
+    }
+    hipLaunchKernelGGL(k_segsort, dim3(blocks_for(g.ncell, kBlock / 64)), dim3(kBlock), 0,
+                       ctx->stream, offsets, g.ncell, perm, s.large_list, s.large_count, x, y, z,
+                       m, sorted, chunk_count);
+    if ((rc = sr_check_launch(ctx, "k_segsort")))
+        return rc;
+    if (n > kLargeCell) {
+        int max_large = n / (kLargeCell + 1) + 1;
+        int grid = max_large < 2048 ? max_large : 2048;
+        hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kBlock), 0, ctx->stream, offsets,
+                           perm, s.tmp, s.large_list, s.large_count, x, y, z, m, sorted);
+        if ((rc = sr_check_launch(ctx, "k_segsort_large")))
+            return rc;
+    }
+    return SR_OK;
+}
+
+extern "C" int sr_bin(sr_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
+                      const sr_box *box, double cell, int32_t *cell_offsets, int32_t *perm)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > INT_MAX)
+        return sr_fail(ctx, SR_EINVAL, "n=%lld out of range", (long long)n);
+    if (!cell_offsets || (n > 0 && (!x || !y || !z || !perm)))
+        return sr_fail(ctx, SR_EINVAL, "NULL pointer");
+    Geom g;
+    int rc = sr_make_geom(ctx, box, cell, &g);
+    if (rc)
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    Bump sz{nullptr, 0, 0};
+    BinScratch s;
+    bin_layout(sz, n, g, s);
+    if ((rc = sr_arena_reserve(ctx, sz.off)))
+        return rc;
+    Bump b{ctx->arena, 0, ctx->arena_cap};
+    bin_layout(b, n, g, s);
+    return bin_enqueue(ctx, x, y, z, nullptr, (int)n, g, s, cell_offsets, perm, nullptr, nullptr);
+}

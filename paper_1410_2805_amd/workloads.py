@@ -118,7 +118,7 @@ def zeldovich(ngrid: int, L: float, seed: int, rms: float = 0.5) -> Particles:
     shape = (ngrid, ngrid, ngrid)
     disp = []
     for kc in (kx, ky, kz):
-        comp = np.fft.irfftn(1j * kc * dk * inv_k2, s=shape)
+        comp = np.fft.irfftn(1j * kc * dk * inv_k2, s=shape, axes=(0, 1, 2))
         disp.append(comp.reshape(-1))
     del dk
     psi = np.stack(disp, axis=1)

@@ -1,0 +1,47 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry
+point the header declares, and its host-only geometry calls behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "sr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sr_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1410_2805_amd import sr
+    lib = ctypes.CDLL(sr.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 10
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(sr.exported_symbols()) <= set(names)
+
+
+def test_grid_dims_and_scratch():
+    from paper_1410_2805_amd import sr
+    dims, nc = sr.sr_grid_dims(sr.Box.make(128.0), 3.0)
+    assert dims == (42, 42, 42) and nc == 42 ** 3
+    dims, nc = sr.sr_grid_dims(sr.Box.make((32.0, 64.0, 9.0)), 3.0)
+    assert dims == (10, 21, 3) and nc == 630
+    with pytest.raises(sr.SRError):
+        sr.sr_grid_dims(sr.Box.make(2.0), 3.0)
+    with pytest.raises(sr.SRError):
+        sr.sr_grid_dims(sr.Box.make(10.0), 0.0)
+    b1 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, True)
+    b0 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, False)
+    assert b1 > b0 > 2 ** 21 * 8
+
+
+def test_null_context_is_rejected():
+    from paper_1410_2805_amd import sr
+    assert sr.lib.sr_sync(None) == sr.SR_EINVAL
+    assert sr.lib.sr_ctx_destroy(None) == sr.SR_EINVAL
+    assert sr.lib.sr_bin(None, None, None, None, 0, None, 3.0, None, None) == sr.SR_EINVAL

@@ -1,0 +1,194 @@
+"""sr_force on the GPU against the FP64 brute-force oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1410_2805_amd import gridfit
+from paper_1410_2805_amd import workloads as W
+from tests.parity import accel_np, check_accel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+R_MAX, EPS = 3.0, 0.1
+
+
+@pytest.fixture(scope="module")
+def sr():
+    from paper_1410_2805_amd import sr as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(sr):
+    c = sr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def poly():
+    return gridfit.poly_coeffs()
+
+
+def _gpu_force(sr, ctx, p, cell, poly, eps=EPS, r_max=R_MAX, momentum=False):
+    t = to_dev(p)
+    box = sr.Box.make(p.L, periodic=p.periodic, skin=p.skin)
+    ax, ay, az, mom = sr.sr_force(ctx, t["x"], t["y"], t["z"], t["m"], box, cell, r_max, eps,
+                                  poly, momentum=momentum)
+    ctx.sync()
+    return accel_np(ax, ay, az), (mom.cpu().numpy() if mom is not None else None)
+
+
+def _ref(p, poly, targets=None, eps=EPS, r_max=R_MAX):
+    return O.force(p.x, p.y, p.z, p.m, p.L, r_max, eps, poly.astype(np.float64),
+                   periodic=p.periodic, skin=p.skin, targets=targets)
+
+
+def test_uniform_32k_full(sr, ctx, poly):
+    """The plain single-box workload, every particle against the full N^2 oracle."""
+    p = W.config("uniform32")
+    a, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    st = check_accel(a, _ref(p, poly), "uniform32")
+    print("uniform32", st)
+
+
+@pytest.mark.parametrize("L,cell,n,seed", [(16.0, 3.0, 4096, 1), (9.5, 3.0, 900, 2),
+                                           (20.0, 4.0, 8000, 3), (24.0, 6.0, 13000, 4),
+                                           (13.0, 3.25, 2197, 5)])
+def test_uniform_small_boxes(sr, ctx, poly, L, cell, n, seed):
+    p = W.uniform(n, L, seed)
+    p.m = np.random.default_rng(seed).uniform(0.25, 4.0, n).astype(np.float32)
+    a, _ = _gpu_force(sr, ctx, p, cell, poly)
+    check_accel(a, _ref(p, poly), "L=%g cell=%g" % (L, cell))
+
+
+def test_clustered_periodic(sr, ctx, poly):
+    """Dense halos: cells of hundreds to thousands of particles, chunked."""
+    p = W.nfw_share(30000, 30.0, 8, periodic=True, halo_cap=3000)
+    a, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    check_accel(a, _ref(p, poly), "clustered")
+
+
+def test_open_box_with_skin(sr, ctx, poly):
+    p = W.nfw_share(20000, 27.0, 9, skin=3.0)
+    a, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    ref = _ref(p, poly)
+    assert ref["passive"].sum() > 0
+    check_accel(a, ref, "open box")
+    assert np.all(a[ref["passive"]] == 0.0)
+
+
+def test_cell_size_independence(sr, ctx, poly):
+    p = W.uniform(6000, 24.0, 12)
+    ref = _ref(p, poly)
+    outs = []
+    for cell in (3.0, 4.0, 6.0):
+        a, _ = _gpu_force(sr, ctx, p, cell, poly)
+        check_accel(a, ref, "cell %g" % cell)
+        outs.append(a)
+    # different tilings reorder the sums only (cutoff ties aside)
+    calm = ref["A"] == 0
+    assert np.max(np.abs(outs[0] - outs[2])[calm]) < 1e-4
+
+
+def test_determinism_and_momentum(sr, ctx, poly):
+    p = W.uniform(20000, 28.0, 13)
+    a1, m1 = _gpu_force(sr, ctx, p, 3.0, poly, momentum=True)
+    a2, m2 = _gpu_force(sr, ctx, p, 3.0, poly, momentum=True)
+    assert np.array_equal(a1, a2) and np.array_equal(m1, m2)
+    ref = _ref(p, poly)
+    # Newton's third law in a periodic box: sum m a ~ 0 within float32 sums
+    assert np.linalg.norm(m1) <= 1e-6 * float(np.sum(ref["S"]))
+    want = (p.m.astype(np.float64)[:, None] * a1).sum(0)
+    assert np.allclose(m1, want, rtol=0, atol=1e-9 * float(np.abs(a1).sum()))
+
+
+def test_shuffle_and_translation_invariance(sr, ctx, poly):
+    p = W.uniform(8000, 18.0, 14)
+    a, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(p.n)
+    q = W.Particles(p.x[order].copy(), p.y[order].copy(), p.z[order].copy(), p.m[order].copy(),
+                    p.L)
+    aq, _ = _gpu_force(sr, ctx, q, 3.0, poly)
+    ref = _ref(p, poly)
+    check_accel(aq[np.argsort(order)], ref, "shuffled")
+    sh = np.mod(p.pos64() + np.array([4.5, -9.0, 13.5]), 18.0).astype(np.float32)
+    r = W.Particles(sh[:, 0].copy(), sh[:, 1].copy(), sh[:, 2].copy(), p.m.copy(), p.L)
+    ar, _ = _gpu_force(sr, ctx, r, 3.0, poly)
+    check_accel(ar, _ref(r, poly), "translated")
+
+
+def test_edge_cases(sr, ctx, poly):
+    # N = 0 and N = 1
+    e = W.Particles(*(np.zeros(0, np.float32) for _ in range(4)), 12.0)
+    a, _ = _gpu_force(sr, ctx, e, 3.0, poly)
+    assert a.shape == (0, 3)
+    one = W.Particles(np.array([5.0], np.float32), np.array([6.0], np.float32),
+                      np.array([7.0], np.float32), np.ones(1, np.float32), 12.0)
+    a, _ = _gpu_force(sr, ctx, one, 3.0, poly)
+    assert np.all(a == 0)
+    # a pair straddling the periodic corner in all three axes
+    two = W.Particles(np.array([0.2, 11.5], np.float32), np.array([0.3, 11.9], np.float32),
+                      np.array([11.7, 0.1], np.float32), np.ones(2, np.float32), 12.0)
+    a, _ = _gpu_force(sr, ctx, two, 3.0, poly)
+    check_accel(a, _ref(two, poly), "corner pair")
+    # coincident particles (zero separation between distinct particles)
+    co = W.Particles(np.array([3.0, 3.0, 4.0], np.float32), np.array([3.0, 3.0, 3.0], np.float32),
+                     np.array([3.0, 3.0, 3.0], np.float32), np.ones(3, np.float32), 12.0)
+    a, _ = _gpu_force(sr, ctx, co, 3.0, poly)
+    check_accel(a, _ref(co, poly), "coincident")
+
+
+def test_invalid_args(sr, ctx, poly):
+    p = W.uniform(100, 12.0, 1)
+    t = to_dev(p)
+    args = (t["x"], t["y"], t["z"], t["m"])
+    with pytest.raises(sr.SRError):  # r_max larger than the cell
+        sr.sr_force(ctx, *args, sr.Box.make(12.0), 3.0, 3.5, EPS, poly)
+    with pytest.raises(sr.SRError):  # eps <= 0
+        sr.sr_force(ctx, *args, sr.Box.make(12.0), 3.0, 3.0, 0.0, poly)
+    with pytest.raises(sr.SRError):  # periodic with fewer than 3 cells
+        sr.sr_force(ctx, *args, sr.Box.make((12.0, 12.0, 5.0)), 2.5, 2.0, EPS, poly)
+
+
+def test_pair_stats_match_oracle(sr, ctx, poly):
+    p = W.uniform(10000, 21.0, 15)
+    t = to_dev(p)
+    box = sr.Box.make(p.L)
+    useful, cand, per = sr.sr_pair_stats(ctx, t["x"], t["y"], t["z"], box, 3.0, R_MAX,
+                                         per_target=True)
+    ref = _ref(p, poly)
+    per = per.cpu().numpy()
+    tie = ref["A"] > 0
+    assert np.array_equal(per[~tie], ref["npair"][~tie])
+    assert abs(useful - int(ref["npair"].sum())) <= int(tie.sum()) * 2
+    assert cand > useful
+
+
+@pytest.mark.slow
+def test_zeldovich_128_sampled(sr, ctx, poly):
+    """Full 128^3 Zel'dovich box as timed by the benchmark, checked on a seeded
+    sample of targets against the O(N) oracle scan."""
+    p = W.config("zeldovich128")
+    a, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    tg = np.sort(np.random.default_rng(77).choice(p.n, 2048, replace=False))
+    st = check_accel(a[tg], _ref(p, poly, targets=tg), "zeldovich128")
+    print("zeldovich128 sampled", st)
+
+
+@pytest.mark.slow
+def test_nfw_256_sampled(sr, ctx, poly):
+    """256^3 clustered open share with a passive skin, sampled targets
+    (half drawn from the densest cells)."""
+    p = W.config("nfw256")
+    a, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    rng = np.random.default_rng(78)
+    _, _, cid = O.bin(p.x, p.y, p.z, 256.0, 3.0)
+    counts = np.bincount(cid)
+    dense = np.nonzero(counts[cid] >= np.sort(counts)[-50])[0]
+    tg = np.unique(np.concatenate([rng.choice(p.n, 128, replace=False),
+                                   rng.choice(dense, 128, replace=False)]))
+    st = check_accel(a[tg], _ref(p, poly, targets=tg), "nfw256")
+    print("nfw256 sampled", st)
