@@ -28,6 +28,7 @@ below stand in for them with the same shapes and distributions:
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 
 import numpy as np
@@ -270,8 +271,10 @@ def serving_trace(nreq: int = 2000, rate: float = 200.0, seed: int = 5,
     return [Request(i, float(t[i]), int(ng[i]), int(seed * 100000 + i), steps) for i in range(nreq)]
 
 
+@functools.lru_cache(maxsize=2)
 def config(name: str) -> Particles:
-    """The standard single-box workloads by name."""
+    """The standard single-box workloads by name (cached: callers must not
+    modify the returned arrays)."""
     if name == "uniform32":
         return uniform(32 ** 3, 32.0, 1)
     if name == "zeldovich128":
