@@ -86,8 +86,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="zeldovich128", choices=sorted(WORKLOADS))
     ap.add_argument("--cell", type=float, default=3.0)
+    ap.add_argument("--xsplit", type=int, default=0, help="pair-loop x sub-cells (0: library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one 256 MiB device-to-device copy (a known-size kernel "
+                         "for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,6 +105,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log("generating %s" % args.workload)
     p = workloads.config(args.workload)
     poly = gridfit.poly_coeffs()
@@ -108,6 +118,9 @@ def main():
     box = sr.Box.make(p.L, periodic=p.periodic, skin=p.skin)
     arena = sr.sr_scratch_bytes(box, args.cell, p.n, True)
     ctx = sr.Context(0, arena_bytes=arena)
+    if args.xsplit:
+        ctx.set_tuning(args.xsplit)
+    xsplit = ctx.get_tuning()["xsplit"]
     out = tuple(torch.empty(p.n, dtype=torch.float32, device=dev) for _ in range(3))
     mom = torch.zeros(3, dtype=torch.float64, device=dev)
 
@@ -164,6 +177,7 @@ def main():
             "name": args.workload,
             "n": p.n,
             "cell": args.cell,
+            "xsplit": xsplit,
             "useful_pairs": useful,
             "candidate_pairs": cand,
             "waste": cand / max(useful, 1),

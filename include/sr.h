@@ -164,6 +164,20 @@ int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const float *z, i
                   const sr_box *box, double cell, float r_max, int32_t *per_target,
                   int64_t *useful, int64_t *candidates);
 
+/* Tuning of the pair loop of sr_force (results are the same up to float32
+ * summation order for every setting):
+ *   xsplit : 1..4 sub-cells per chaining cell along x.  The x-contiguous rows
+ *            of the 27-cell search then span 2 + 1/xsplit chaining cells
+ *            instead of 3, so fewer candidate pairs are tested; work items
+ *            get smaller.  Default 2. */
+typedef struct sr_tuning {
+    int32_t xsplit;
+    int32_t _reserved[3];
+} sr_tuning;
+
+int sr_set_tuning(sr_ctx *ctx, const sr_tuning *t);
+int sr_get_tuning(const sr_ctx *ctx, sr_tuning *t);
+
 /* Device-side timing of sr_force (a measurement helper).  While enabled,
  * each sr_force call records HIP events on the context's stream: one before
  * its preparation (binning, gather, work items), one before the pair-loop

@@ -80,29 +80,51 @@ __global__ __launch_bounds__(kBlock) void k_cellid(const float *__restrict__ x,
                                                    int *__restrict__ cid, int *__restrict__ slot,
                                                    int *__restrict__ count, int *__restrict__ status)
 {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n)
-        return;
-    const float p[3] = {x[i], y[i], z[i]};
-    int c[3];
-    bool bad = false;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool live = i < n;
+    int id = 0;
+    if (live) {
+        const float p[3] = {x[i], y[i], z[i]};
+        int c[3];
+        bool bad = false;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double v = (double)p[d];
-        if (!(v >= 0.0 && v < g.len[d])) {  // also catches NaN
-            bad = true;
-            c[d] = 0;
-        } else {
-            double t = floor(v * g.inv[d]);
-            int ci = (int)t;
-            c[d] = ci < g.nc[d] - 1 ? ci : g.nc[d] - 1;
+        for (int d = 0; d < 3; ++d) {
+            double v = (double)p[d];
+            if (!(v >= 0.0 && v < g.len[d])) {  // also catches NaN
+                bad = true;
+                c[d] = 0;
+            } else {
+                double t = floor(v * g.inv[d]);
+                int ci = (int)t;
+                c[d] = ci < g.nc[d] - 1 ? ci : g.nc[d] - 1;
+            }
         }
+        if (bad)
+            atomicOr(status, 1);
+        id = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+        cid[i] = id;
     }
-    if (bad)
-        atomicOr(status, 1);
-    int id = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
-    cid[i] = id;
-    slot[i] = atomicAdd(&count[id], 1);
+    // Spatially ordered input puts many lanes of a wavefront in one cell:
+    // lanes sharing the first few distinct ids take one atomic per id.
+    unsigned long long todo = __ballot(live);
+    int my = -1;
+    for (int round = 0; round < 4 && todo; ++round) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lid = __shfl(id, leader, 64);
+        const unsigned long long peers = __ballot(live && id == lid) & todo;
+        int base = 0;
+        if (lane == leader)
+            base = atomicAdd(&count[lid], __popcll(peers));
+        base = __shfl(base, leader, 64);
+        if ((peers >> lane) & 1ull)
+            my = base + __popcll(peers & ((1ull << lane) - 1ull));
+        todo &= ~peers;
+    }
+    if (live && my < 0)
+        my = atomicAdd(&count[id], 1);
+    if (live)
+        slot[i] = my;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int *__restrict__ in, int m,
@@ -224,7 +246,8 @@ __global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offs
                                                     const float *__restrict__ z,
                                                     const float *__restrict__ m,
                                                     float4 *__restrict__ sorted,
-                                                    int *__restrict__ chunk_count)
+                                                    int *__restrict__ chunk_count,
+                                                    int *__restrict__ mass_mixed)
 {
     __shared__ int buf[kBlock / 64][kLargeCell];
     const int lane = threadIdx.x & 63;
@@ -235,15 +258,20 @@ __global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offs
     const int b = offsets[cell];
     const int len = offsets[cell + 1] - b;
     if (chunk_count && lane == 0)
-        chunk_count[cell] = (len + kChunk - 1) / kChunk;
+        chunk_count[cell] = chunks_for(len);
     if (len <= 64) {
         int v = lane < len ? perm[b + lane] : INT_MAX;
         v = bitonic64(v, lane);
+        bool mixed = false;
         if (lane < len) {
             perm[b + lane] = v;
-            if (sorted)
+            if (sorted) {
                 gather_one(sorted, b + lane, v, x, y, z, m);
+                mixed = m[v] != m[0];
+            }
         }
+        if (__any(mixed) && lane == 0)
+            atomicOr(mass_mixed, 1);
     } else if (len <= kLargeCell) {
         int P = 128;
         while (P < len)
@@ -253,12 +281,17 @@ __global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offs
             sb[t] = t < len ? perm[b + t] : INT_MAX;
         wave_sync();
         lds_bitonic(sb, P, lane);
+        bool mixed = false;
         for (int t = lane; t < len; t += 64) {
             int v = sb[t];
             perm[b + t] = v;
-            if (sorted)
+            if (sorted) {
                 gather_one(sorted, b + t, v, x, y, z, m);
+                mixed = mixed || m[v] != m[0];
+            }
         }
+        if (__any(mixed) && lane == 0)
+            atomicOr(mass_mixed, 1);
     } else if (lane == 0) {
         int k = atomicAdd(large_count, 1);
         large_list[k] = cell;
@@ -277,7 +310,8 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(const int *__restrict_
                                                           const float *__restrict__ y,
                                                           const float *__restrict__ z,
                                                           const float *__restrict__ m,
-                                                          float4 *__restrict__ sorted)
+                                                          float4 *__restrict__ sorted,
+                                                          int *__restrict__ mass_mixed)
 {
     __shared__ int buf[kLargeCell];
     const int nl = *large_count;
@@ -350,8 +384,14 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(const int *__restrict_
             __syncthreads();
         }
         if (sorted) {
-            for (int e = threadIdx.x; e < len; e += kBlock)
-                gather_one(sorted, b + e, perm[b + e], x, y, z, m);
+            bool mixed = false;
+            for (int e = threadIdx.x; e < len; e += kBlock) {
+                const int v = perm[b + e];
+                gather_one(sorted, b + e, v, x, y, z, m);
+                mixed = mixed || m[v] != m[0];
+            }
+            if (mixed)
+                atomicOr(mass_mixed, 1);
         }
         __syncthreads();
     }
@@ -401,6 +441,7 @@ void bin_layout(Bump &b, int64_t n, const Geom &g, BinScratch &s)
     s.tmp = b.take<int>(nn);
     s.large_list = b.take<int>(nn / (kLargeCell + 1) + 1);
     s.large_count = b.take<int>(1);
+    s.mass_mixed = b.take<int>(1);
 }
 
 // Enqueue the whole binning pass.  sorted/m and chunk_count may be NULL.
@@ -412,6 +453,8 @@ int bin_enqueue(sr_ctx *ctx, const float *x, const float *y, const float *z, con
     if ((rc = fill_enqueue(ctx, s.count, 0, g.ncell)))
         return rc;
     if ((rc = fill_enqueue(ctx, s.large_count, 0, 1)))
+        return rc;
+    if ((rc = fill_enqueue(ctx, s.mass_mixed, 0, 1)))
         return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_cellid, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
@@ -429,14 +472,15 @@ int bin_enqueue(sr_ctx *ctx, const float *x, const float *y, const float *z, con
     }
     hipLaunchKernelGGL(k_segsort, dim3(blocks_for(g.ncell, kBlock / 64)), dim3(kBlock), 0,
                        ctx->stream, offsets, g.ncell, perm, s.large_list, s.large_count, x, y, z,
-                       m, sorted, chunk_count);
+                       m, sorted, chunk_count, s.mass_mixed);
     if ((rc = sr_check_launch(ctx, "k_segsort")))
         return rc;
     if (n > kLargeCell) {
         int max_large = n / (kLargeCell + 1) + 1;
         int grid = max_large < 2048 ? max_large : 2048;
         hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kBlock), 0, ctx->stream, offsets,
-                           perm, s.tmp, s.large_list, s.large_count, x, y, z, m, sorted);
+                           perm, s.tmp, s.large_list, s.large_count, x, y, z, m, sorted,
+                           s.mass_mixed);
         if ((rc = sr_check_launch(ctx, "k_segsort_large")))
             return rc;
     }

@@ -49,7 +49,7 @@ extern "C" int sr_grid_dims(const sr_box *box, double cell, int32_t dims[3], int
     return SR_OK;
 }
 
-int sr_make_geom(sr_ctx *ctx, const sr_box *box, double cell, Geom *g)
+int sr_make_geom(sr_ctx *ctx, const sr_box *box, double cell, Geom *g, int xsplit)
 {
     int32_t dims[3];
     int64_t nc = 0;
@@ -58,6 +58,13 @@ int sr_make_geom(sr_ctx *ctx, const sr_box *box, double cell, Geom *g)
     if (sr_grid_dims(box, cell, dims, &nc) != SR_OK)
         return sr_fail(ctx, SR_EINVAL, "bad geometry: len=(%g,%g,%g) cell=%g", box->len[0],
                        box->len[1], box->len[2], cell);
+    if (xsplit < 1 || xsplit > kMaxXsplit)
+        return sr_fail(ctx, SR_EINVAL, "xsplit %d out of [1, %d]", xsplit, kMaxXsplit);
+    if ((int64_t)dims[0] * xsplit * dims[1] * dims[2] > 2147483646LL)
+        return sr_fail(ctx, SR_EINVAL, "too many cells");
+    dims[0] *= xsplit;
+    nc *= xsplit;
+    g->hx = xsplit;
     for (int d = 0; d < 3; ++d) {
         g->len[d] = box->len[d];
         g->inv[d] = (double)dims[d] / box->len[d];
@@ -180,6 +187,25 @@ void sr_timing_mark(sr_ctx *ctx, int rec, int which)
 {
     if (rec >= 0)
         (void)hipEventRecord(ctx->events[3 * (size_t)rec + which], ctx->stream);
+}
+
+extern "C" int sr_set_tuning(sr_ctx *ctx, const sr_tuning *t)
+{
+    if (!ctx || !t)
+        return SR_EINVAL;
+    if (t->xsplit < 1 || t->xsplit > kMaxXsplit)
+        return sr_fail(ctx, SR_EINVAL, "xsplit must be in [1, %d]", kMaxXsplit);
+    ctx->xsplit = t->xsplit;
+    return SR_OK;
+}
+
+extern "C" int sr_get_tuning(const sr_ctx *ctx, sr_tuning *t)
+{
+    if (!ctx || !t)
+        return SR_EINVAL;
+    t->xsplit = ctx->xsplit;
+    t->_reserved[0] = t->_reserved[1] = t->_reserved[2] = 0;
+    return SR_OK;
 }
 
 extern "C" int sr_timing_enable(sr_ctx *ctx, int enable)

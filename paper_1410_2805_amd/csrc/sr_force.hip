@@ -70,21 +70,22 @@ __device__ void build_stencil(Stencil &st, const int *__restrict__ offsets, cons
         int x0 = 0, x1 = -1;
         float shx = F[0];
         const int n0 = g.nc[0];
+        const int lo = cx - g.hx, hi = cx + g.hx;
         if (ok) {
             if (g.periodic) {
-                if (cx == 0) {
-                    if (half == 0) { x0 = 0; x1 = 1; }
-                    else { x0 = x1 = n0 - 1; shx -= g.lenf[0]; }
-                } else if (cx == n0 - 1) {
-                    if (half == 0) { x0 = n0 - 2; x1 = n0 - 1; }
-                    else { x0 = x1 = 0; shx += g.lenf[0]; }
+                if (lo < 0) {
+                    if (half == 0) { x0 = 0; x1 = hi; }
+                    else { x0 = lo + n0; x1 = n0 - 1; shx -= g.lenf[0]; }
+                } else if (hi >= n0) {
+                    if (half == 0) { x0 = lo; x1 = n0 - 1; }
+                    else { x0 = 0; x1 = hi - n0; shx += g.lenf[0]; }
                 } else if (half == 0) {
-                    x0 = cx - 1;
-                    x1 = cx + 1;
+                    x0 = lo;
+                    x1 = hi;
                 }
             } else if (half == 0) {
-                x0 = cx > 0 ? cx - 1 : 0;
-                x1 = cx < n0 - 1 ? cx + 1 : n0 - 1;
+                x0 = lo > 0 ? lo : 0;
+                x1 = hi < n0 - 1 ? hi : n0 - 1;
             }
         }
         if (x1 >= x0) {
@@ -105,6 +106,18 @@ __device__ void build_stencil(Stencil &st, const int *__restrict__ offsets, cons
     }
     if (lane == 0)
         st.pbeg[18] = total;
+}
+
+// A target whose stencil wraps past the upper face of an axis works in a
+// frame shifted by -L along it: its coordinate and the unwrapped sources are
+// all >= L/2 there, so subtracting L is exact, and the wrapped sources need
+// no shift at all.
+__device__ __forceinline__ void frame_shift(const Geom &g, const int cc[3], float F[3])
+{
+    const int h[3] = {g.hx, 1, 1};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        F[d] = (g.periodic && cc[d] + h[d] >= g.nc[d]) ? -g.lenf[d] : 0.f;
 }
 
 __device__ __forceinline__ void decode_cell(int cell, const Geom &g, int &cx, int &cy, int &cz)
@@ -147,98 +160,121 @@ __device__ __forceinline__ void stage_tile(float4 *tile, const Stencil &st,
     }
 }
 
-__device__ __forceinline__ int split_factor(int nt)
+// One tile of pair interactions for one lane: sources src[0 .. cnt) (cnt a
+// multiple of 4), target (xi, yi, zi); partial sums into tx, ty, tz.
+template <bool kUniformMass>
+__device__ __forceinline__ void pair_tile(const float4 *src, int cnt, float xi, float yi, float zi,
+                                          const ForceParams &fp, float &tx, float &ty, float &tz)
 {
-    int S = 1;
-    while (S < 16 && nt * (S * 2) <= 64)
-        S <<= 1;
-    return S;
+    const float eps = fp.eps, rcut = fp.rcut, q0 = fp.q0;
+    const float n1 = fp.nq[1], n2 = fp.nq[2], n3 = fp.nq[3], n4 = fp.nq[4], n5 = fp.nq[5];
+    for (int j = 0; j < cnt; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float4 s = src[j + u];
+            const float dx = s.x - xi;
+            const float dy = s.y - yi;
+            const float dz = s.z - zi;
+            // se = s + eps; f = se^(-3/2) - q(se) with q(se) = p(se - eps)
+            const float se = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+            const float rs = __builtin_amdgcn_rsqf(se);
+            const float rs2 = rs * rs;
+            const float tt = fmaf(rs2, rs, -q0);
+            float h = fmaf(n5, se, n4);
+            h = fmaf(h, se, n3);
+            h = fmaf(h, se, n2);
+            h = fmaf(h, se, n1);
+            float f = fmaf(h, se, tt);
+            f = se < rcut ? f : 0.f;  // cutoff by select: also zeroes padding
+            if (!kUniformMass)
+                f *= s.w;
+            tx = fmaf(f, dx, tx);
+            ty = fmaf(f, dy, ty);
+            tz = fmaf(f, dz, tz);
+        }
+    }
 }
 
+// One wavefront per work item (a chunk of nt <= 64 targets of one cell).
+// Lane L serves target t = L mod nt in group part = L / nt; the S groups
+// split each staged tile into S contiguous slices.
 __global__ __launch_bounds__(64) void k_force(const int4 *__restrict__ items,
                                               const int *__restrict__ n_items,
                                               const float4 *__restrict__ sorted,
                                               const int *__restrict__ offsets,
-                                              const int *__restrict__ perm, Geom g, ForceParams fp,
-                                              float *__restrict__ ax, float *__restrict__ ay,
-                                              float *__restrict__ az)
+                                              const int *__restrict__ perm,
+                                              const int *__restrict__ mass_mixed, Geom g,
+                                              ForceParams fp, float *__restrict__ ax,
+                                              float *__restrict__ ay, float *__restrict__ az)
 {
-    __shared__ float4 tile[kTile];
+    __shared__ float4 tile[kTile + 4 * kMaxSplit];
     __shared__ Stencil st;
     const int lane = threadIdx.x;
-    // consecutive items (neighbouring cells, shared sources) go to one XCD
-    const int per = gridDim.x >> 3;
+    // Workgroups are dealt to the 8 XCDs round-robin; give XCD k the k-th
+    // contiguous eighth of the items so that neighbouring cells, which share
+    // most of their sources, meet in the same L2.
+    const int nitems = *n_items;
+    const int per = (nitems + 7) >> 3;
     const int it = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (it >= *n_items)
+    if ((int)(blockIdx.x >> 3) >= per || it >= nitems)
         return;
     const int4 item = items[it];
-    const int cell = item.x, kb = item.y, nt = item.z;
+    const int cell = item.x, kb = item.y, nt = item.z, S = item.w;
     int cx, cy, cz;
     decode_cell(cell, g, cx, cy, cz);
     const int cc[3] = {cx, cy, cz};
     float F[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-        F[d] = (g.periodic && cc[d] == g.nc[d] - 1) ? -g.lenf[d] : 0.f;
+    frame_shift(g, cc, F);
     build_stencil(st, offsets, g, cx, cy, cz, F, lane);
 
-    const int S = split_factor(nt);
-    const int G = 64 / S;
-    const int t = lane & (G - 1);
-    const int part = lane / G;
-    const bool has_target = t < nt;
-    const float4 pt = sorted[kb + (has_target ? t : 0)];
+    const int part = lane / nt;
+    const int t = lane - part * nt;
+    const bool has_target = part < S;
+    const float4 pt = sorted[kb + t];
     const bool pas = is_passive(pt, g);
     const float xi = pt.x + F[0], yi = pt.y + F[1], zi = pt.z + F[2];
+    const bool uniform = *mass_mixed == 0;
     __syncthreads();
 
     float acx = 0.f, acy = 0.f, acz = 0.f;
     if (__any(has_target && !pas)) {
-        const float eps = fp.eps, rcut = fp.rcut, q0 = fp.q0;
-        const float n1 = fp.nq[1], n2 = fp.nq[2], n3 = fp.nq[3], n4 = fp.nq[4], n5 = fp.nq[5];
         const int total = st.pbeg[18];
+        const int quantum = 4 * S;
         int p = 0;
         for (int g0 = 0; g0 < total; g0 += kTile) {
             const int cnt = total - g0 < kTile ? total - g0 : kTile;
-            const int cntp = (cnt + 63) & ~63;
+            const int cntp = (cnt + quantum - 1) / quantum * quantum;
             stage_tile(tile, st, sorted, g0, cnt, cntp, lane, p);
             __syncthreads();
+            const int slice = cntp / S;
+            const float4 *src = tile + (has_target ? part : 0) * slice;
             float tx = 0.f, ty = 0.f, tz = 0.f;
-            for (int j0 = part; j0 < cntp; j0 += 4 * S) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float4 s = tile[j0 + u * S];
-                    const float dx = s.x - xi;
-                    const float dy = s.y - yi;
-                    const float dz = s.z - zi;
-                    const float se = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-                    const float rs = __builtin_amdgcn_rsqf(se);
-                    const float rs2 = rs * rs;
-                    const float tt = fmaf(rs2, rs, -q0);
-                    float h = fmaf(n5, se, n4);
-                    h = fmaf(h, se, n3);
-                    h = fmaf(h, se, n2);
-                    h = fmaf(h, se, n1);
-                    float f = fmaf(h, se, tt);
-                    f = se < rcut ? f : 0.f;
-                    f *= s.w;
-                    tx = fmaf(f, dx, tx);
-                    ty = fmaf(f, dy, ty);
-                    tz = fmaf(f, dz, tz);
-                }
-            }
+            if (uniform)
+                pair_tile<true>(src, slice, xi, yi, zi, fp, tx, ty, tz);
+            else
+                pair_tile<false>(src, slice, xi, yi, zi, fp, tx, ty, tz);
             acx += tx;
             acy += ty;
             acz += tz;
             __syncthreads();
         }
+        if (uniform) {
+            acx *= pt.w;
+            acy *= pt.w;
+            acz *= pt.w;
+        }
     }
-    for (int o = G; o < 64; o <<= 1) {
-        acx += __shfl_xor(acx, o, 64);
-        acy += __shfl_xor(acy, o, 64);
-        acz += __shfl_xor(acz, o, 64);
-    }
-    if (part == 0 && has_target) {
+    // add the S group sums of each target in group order
+    float4 *red = tile;
+    red[lane] = make_float4(acx, acy, acz, 0.f);
+    __syncthreads();
+    if (part == 0) {
+        for (int q = 1; q < S; ++q) {
+            const float4 o = red[t + q * nt];
+            acx += o.x;
+            acy += o.y;
+            acz += o.z;
+        }
         const int orig = perm[kb + t];
         ax[orig] = pas ? 0.f : acx;
         ay[orig] = pas ? 0.f : acy;
@@ -267,9 +303,7 @@ __global__ __launch_bounds__(64) void k_pair_stats(const int4 *__restrict__ item
     decode_cell(cell, g, cx, cy, cz);
     const int cc[3] = {cx, cy, cz};
     float F[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-        F[d] = (g.periodic && cc[d] == g.nc[d] - 1) ? -g.lenf[d] : 0.f;
+    frame_shift(g, cc, F);
     build_stencil(st, offsets, g, cx, cy, cz, F, lane);
     const bool has_target = lane < nt;
     const float4 pt = sorted[kb + (has_target ? lane : 0)];
@@ -322,7 +356,7 @@ __global__ void k_items(const int *__restrict__ offsets, const int *__restrict__
     for (int k = 0; k < q; ++k) {
         const int lo = (int)((long long)k * len / q);
         const int hi = (int)((long long)(k + 1) * len / q);
-        items[item_off[c] + k] = make_int4(c, b + lo, hi - lo, 0);
+        items[item_off[c] + k] = make_int4(c, b + lo, hi - lo, split_for(hi - lo));
     }
 }
 
@@ -382,7 +416,7 @@ struct ForceScratch {
 int64_t item_bound(int64_t n, int ncell)
 {
     int64_t nonempty = n < ncell ? n : ncell;
-    return nonempty + n / kChunk + 1;
+    return nonempty + n / 16 + 1;  // see chunks_for
 }
 
 void force_layout(Bump &b, int64_t n, const Geom &g, ForceScratch &s)
@@ -420,7 +454,7 @@ int check_force_args(sr_ctx *ctx, const float *x, const float *y, const float *z
     if (rc)
         return rc;
     for (int d = 0; d < 3; ++d) {
-        double cs = g->len[d] / g->nc[d];
+        double cs = g->len[d] / g->nc[d];  // chaining cell width
         if ((double)r_max > cs)
             return sr_fail(ctx, SR_EINVAL,
                            "r_max=%g exceeds the cell width %g on axis %d: 27 cells would not cover the cutoff",
@@ -431,7 +465,8 @@ int check_force_args(sr_ctx *ctx, const float *x, const float *y, const float *z
         if (g->periodic && !(2.0 * (double)r_max < g->len[d]))
             return sr_fail(ctx, SR_EINVAL, "periodic box needs 2 r_max < L");
     }
-    return SR_OK;
+    // the pair loop's own (x-split) mesh
+    return sr_make_geom(ctx, box, cell, g, ctx ? ctx->xsplit : kMaxXsplit);
 }
 
 ForceParams make_params(float r_max, float eps, const float *poly)
@@ -493,7 +528,8 @@ extern "C" int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int w
     if (!bytes || n < 0 || n > INT_MAX)
         return SR_EINVAL;
     Geom g;
-    if (sr_make_geom(nullptr, box, cell, &g))
+    // with_force: the largest x split any context may use
+    if (sr_make_geom(nullptr, box, cell, &g, with_force ? kMaxXsplit : 1))
         return SR_EINVAL;
     Bump sz{nullptr, 0, 0};
     if (with_force) {
@@ -532,8 +568,8 @@ extern "C" int sr_force(sr_ctx *ctx, const float *x, const float *y, const float
     sr_timing_mark(ctx, rec, 1);
     if (n > 0) {
         hipLaunchKernelGGL(k_force, dim3(item_grid(n, g.ncell)), dim3(64), 0, ctx->stream,
-                           s.items, s.item_off + g.ncell, s.sorted, s.offsets, s.perm, g, fp, ax,
-                           ay, az);
+                           s.items, s.item_off + g.ncell, s.sorted, s.offsets, s.perm,
+                           s.bin.mass_mixed, g, fp, ax, ay, az);
         if ((rc = sr_check_launch(ctx, "k_force")))
             return rc;
     }

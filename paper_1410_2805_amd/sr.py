@@ -27,6 +27,12 @@ class SRError(RuntimeError):
         self.code = code
 
 
+class Tuning(ctypes.Structure):
+    """sr_tuning: pair-loop tiling knobs."""
+
+    _fields_ = [("xsplit", ctypes.c_int32), ("_reserved", ctypes.c_int32 * 3)]
+
+
 class Box(ctypes.Structure):
     """sr_box: [0, len)^3, periodic or open with a passive skin."""
 
@@ -66,6 +72,8 @@ def _load():
         "sr_pair_stats": (ctypes.c_int, [P, P, P, P, i64, BP, f64, f32, P,
                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "sr_timing_enable": (ctypes.c_int, [P, ctypes.c_int]),
+        "sr_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
+        "sr_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "sr_timing_collect": (ctypes.c_int, [P, ctypes.POINTER(f64), ctypes.POINTER(f64),
                                              ctypes.POINTER(i64)]),
     }
@@ -82,7 +90,7 @@ lib = _load()
 def exported_symbols() -> list[str]:
     return ["sr_ctx_create", "sr_ctx_destroy", "sr_last_error", "sr_set_stream", "sr_arena_info",
             "sr_sync", "sr_grid_dims", "sr_scratch_bytes", "sr_bin", "sr_force", "sr_pair_stats",
-            "sr_timing_enable", "sr_timing_collect"]
+            "sr_timing_enable", "sr_timing_collect", "sr_set_tuning", "sr_get_tuning"]
 
 
 def _ptr(t):
@@ -155,6 +163,16 @@ class Context:
 
     def sync(self):
         self._check(lib.sr_sync(self._h))
+
+    def set_tuning(self, xsplit: int):
+        t = Tuning()
+        t.xsplit = int(xsplit)
+        self._check(lib.sr_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib.sr_get_tuning(self._h, ctypes.byref(t)))
+        return {"xsplit": int(t.xsplit)}
 
     def timing_enable(self, on: bool = True):
         self._check(lib.sr_timing_enable(self._h, int(bool(on))))

@@ -92,6 +92,28 @@ def test_cell_size_independence(sr, ctx, poly):
     assert np.max(np.abs(outs[0] - outs[2])[calm]) < 1e-4
 
 
+@pytest.mark.parametrize("xsplit", [1, 2, 3, 4])
+def test_xsplit_settings(sr, ctx, poly, xsplit):
+    """Every x sub-cell setting of the pair loop gives the oracle's forces,
+    including boxes with only 3 chaining cells per axis."""
+    before = ctx.get_tuning()["xsplit"]
+    try:
+        ctx.set_tuning(xsplit)
+        for (n, L, cell, seed) in ((5000, 17.0, 3.0, 40 + xsplit), (900, 9.5, 3.0, 50 + xsplit),
+                                   (3000, 14.0, 4.5, 60 + xsplit)):
+            p = W.uniform(n, L, seed)
+            p.m = np.random.default_rng(seed).uniform(0.5, 2.0, n).astype(np.float32)
+            a, _ = _gpu_force(sr, ctx, p, cell, poly)
+            check_accel(a, _ref(p, poly), "xsplit %d L=%g" % (xsplit, L))
+        q = W.nfw_share(8000, 21.0, 70 + xsplit, skin=3.0)
+        a, _ = _gpu_force(sr, ctx, q, 3.0, poly)
+        check_accel(a, _ref(q, poly), "xsplit %d open" % xsplit)
+    finally:
+        ctx.set_tuning(before)
+    with pytest.raises(sr.SRError):
+        ctx.set_tuning(5)
+
+
 def test_determinism_and_momentum(sr, ctx, poly):
     p = W.uniform(20000, 28.0, 13)
     a1, m1 = _gpu_force(sr, ctx, p, 3.0, poly, momentum=True)
