@@ -84,9 +84,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="zeldovich128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="zeldovich128",
+                    choices=sorted(WORKLOADS) + ["batch64", "serving"])
+    ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
+    ap.add_argument("--replays", type=int, default=200, help="batch64: timed graph replays")
     ap.add_argument("--cell", type=float, default=3.0)
     ap.add_argument("--xsplit", type=int, default=0, help="pair-loop x sub-cells (0: library default)")
+    ap.add_argument("--order", type=int, default=-1, help="work-item order (-1: library default)")
+    ap.add_argument("--persistent", type=int, default=-1, help="persistent pair loop (-1: default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -104,6 +109,10 @@ def main():
     from paper_1410_2805_amd import gridfit, sr, workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     dev = torch.device("cuda:0")
     if args.calib_copy:
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -119,8 +128,12 @@ def main():
     arena = sr.sr_scratch_bytes(box, args.cell, p.n, True)
     ctx = sr.Context(0, arena_bytes=arena)
     if args.xsplit:
-        ctx.set_tuning(args.xsplit)
-    xsplit = ctx.get_tuning()["xsplit"]
+        ctx.set_tuning(xsplit=args.xsplit)
+    if args.order >= 0:
+        ctx.set_tuning(order=args.order)
+    if args.persistent >= 0:
+        ctx.set_tuning(persistent=args.persistent)
+    tuning = ctx.get_tuning()
     out = tuple(torch.empty(p.n, dtype=torch.float32, device=dev) for _ in range(3))
     mom = torch.zeros(3, dtype=torch.float64, device=dev)
 
@@ -177,7 +190,7 @@ def main():
             "name": args.workload,
             "n": p.n,
             "cell": args.cell,
-            "xsplit": xsplit,
+            "tuning": tuning,
             "useful_pairs": useful,
             "candidate_pairs": cand,
             "waste": cand / max(useful, 1),
@@ -196,6 +209,141 @@ def main():
             "traffic": None,
         },
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+def bench_batch(args):
+    """64 independent periodic boxes (16^3..96^3 particles, half uniform,
+    half clustered) in one plan: autotuned, captured in a HIP graph, timed
+    per replay; compared with a loop of plain single-box sr_force calls."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2805_amd import gridfit, sr, workloads
+
+    dev = torch.device("cuda:0")
+    poly = gridfit.poly_coeffs()
+    specs = workloads.batch_specs(64, seed=4)
+    log("generating 64 boxes (%d particles)" % sum(s.n for s in specs))
+    boxes = []
+    for sp in specs:
+        p = workloads.make_box(sp)
+        t = {k: torch.from_numpy(getattr(p, k)).to(dev) for k in "xyzm"}
+        t.update({k: torch.empty(p.n, dtype=torch.float32, device=dev) for k in ("ax", "ay", "az")})
+        t["box"] = sr.Box.make(p.L)
+        t["cell"] = 3.0
+        boxes.append(t)
+    ctx = sr.Context(0)
+    useful = 0
+    for t in boxes:
+        u, _, _ = sr.sr_pair_stats(ctx, t["x"], t["y"], t["z"], t["box"], 3.0, R_MAX)
+        useful += u
+    mom = torch.zeros(3 * len(boxes), dtype=torch.float64, device=dev)
+    plan = sr.Plan(ctx, boxes, R_MAX, EPS, poly, momentum=mom)
+    best, best_ms = plan.autotune(reps=3)
+    log("autotuned: %s (%.3f ms)" % (best, best_ms))
+    plan.capture()
+    for _ in range(5):
+        plan.launch()
+    ctx.sync()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.replays)]
+    for e0, e1 in evs:
+        e0.record()
+        plan.launch()
+        e1.record()
+    torch.cuda.synchronize()
+    lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    # baseline: the same boxes by a loop of single-box calls, same tuning
+    ctx.set_tuning(xsplit=best["xsplit"], order=best["order"], persistent=best["persistent"])
+    cell = 3.0 * best["cell_scale"]
+
+    def loop():
+        for t in boxes:
+            sr.sr_force(ctx, t["x"], t["y"], t["z"], t["m"], t["box"], cell, R_MAX, EPS, poly,
+                        out=(t["ax"], t["ay"], t["az"]))
+
+    for _ in range(3):
+        loop()
+    torch.cuda.synchronize()
+    reps = max(10, args.replays // 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        loop()
+    e1.record()
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1) / reps
+    p50 = float(np.percentile(lat, 50))
+    res = {
+        "metric": "batched short-range pass latency (64 boxes, one graph launch)",
+        "value": useful / (p50 * 1e-3),
+        "unit": "useful directed pair interactions/s",
+        "n_gpus": 1, "steps": args.replays, "warmup": 5, "ms_per_step": p50,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 periodic boxes, N log-uniform in [16^3, 96^3] (total %d), "
+                               "half uniform, half NFW-clustered, r_max=3, eps=0.1, cell 3"
+                               % sum(s.n for s in specs),
+                   "tuning": best, "useful_pairs": useful},
+        "latency_ms": {"p50": p50, "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean()), "replays": int(lat.size)},
+        "loop_of_single_box_calls_ms": loop_ms,
+        "speedup_vs_loop": loop_ms / p50,
+    }
+    print(json.dumps(res), flush=True)
+    plan.close()
+    ctx.close()
+
+
+def bench_serving(args):
+    """Poisson-arriving requests (mean 200/s), Zel'dovich boxes of 24^3..128^3
+    particles, 10 SKS steps each, served by continuous batching; then the same
+    trace by a FIFO loop of plain single-box calls."""
+    import torch
+
+    from paper_1410_2805_amd import gridfit, serving, sr, workloads
+
+    poly = gridfit.poly_coeffs()
+    trace = workloads.serving_trace(args.requests, rate=200.0, seed=5)
+    boxes = serving.BoxCache(seed=5)
+    sizes = sorted({r.ngrid for r in trace})
+    log("generating %d distinct boxes" % len(sizes))
+    t0 = time.perf_counter()
+    for k, ng in enumerate(sizes):
+        boxes.get(ng)
+        if time.perf_counter() - t0 > 5:
+            log("  %d/%d" % (k + 1, len(sizes)))
+            t0 = time.perf_counter()
+    ctx = sr.Context(0)
+    srv = sr.Server(ctx, 64 << 30, 64, R_MAX, EPS, poly, 3.0)
+    # warm-up request (compilation, allocator)
+    warm = workloads.serving_trace(4, rate=1000.0, seed=99, ng_lo=24, ng_hi=32)
+    serving.run_server(srv, warm, boxes)
+    log("serving %d requests" % len(trace))
+    r_srv = serving.run_server(srv, trace, boxes, log=log)
+    info = srv.info()
+    srv.close()
+    log("fifo baseline")
+    r_fifo = serving.run_fifo(ctx, trace, boxes, R_MAX, EPS, poly, 3.0, log=log)
+    res = {
+        "metric": "serving latency p50/p99 and throughput (continuous batching)",
+        "value": r_srv["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": len(trace), "warmup": 4,
+        "ms_per_step": 1e3 * r_srv["latency_p50_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%d Poisson requests at 200/s, Zel'dovich boxes N = ngrid^3, "
+                               "ngrid log-uniform in [24, 128], 10 SKS steps (dt 0.05), split "
+                               "coordinates, HBM budget 64 GiB, 64 slots" % len(trace),
+                   "state_bytes_high_water": info["state_bytes_high_water"],
+                   "ticks": r_srv["ticks"]},
+        "server": {k: v for k, v in r_srv.items() if k != "results"},
+        "fifo_baseline": r_fifo,
+        "throughput_ratio_vs_fifo": r_srv["particle_steps_per_s"] / r_fifo["particle_steps_per_s"],
     }
     print(json.dumps(res), flush=True)
     ctx.close()

@@ -164,19 +164,195 @@ int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const float *z, i
                   const sr_box *box, double cell, float r_max, int32_t *per_target,
                   int64_t *useful, int64_t *candidates);
 
-/* Tuning of the pair loop of sr_force (results are the same up to float32
- * summation order for every setting):
- *   xsplit : 1..4 sub-cells per chaining cell along x.  The x-contiguous rows
- *            of the 27-cell search then span 2 + 1/xsplit chaining cells
- *            instead of 3, so fewer candidate pairs are tested; work items
- *            get smaller.  Default 2. */
+/* Tuning of the pair loop (results are the same up to float32 summation
+ * order for every setting; for a fixed setting they are bitwise
+ * reproducible):
+ *   xsplit     : 1..4 sub-cells per chaining cell along x.  The x-contiguous
+ *                rows of the 27-cell search then span 2 + 1/xsplit chaining
+ *                cells instead of 3, so fewer candidate pairs are tested; work
+ *                items get smaller.  Default 2.
+ *   order      : 0 work items in cell order; 1 by decreasing cost bucket
+ *                (longest first), default.
+ *   persistent : 0 one workgroup per work item (default); 1 a fixed grid of
+ *                workgroups takes items from a device counter.
+ *   cell_scale : plans only (sr_plan_*): chaining cell = cell * cell_scale,
+ *                >= 1; ignored by sr_set_tuning. */
 typedef struct sr_tuning {
     int32_t xsplit;
-    int32_t _reserved[3];
+    int32_t order;
+    int32_t persistent;
+    float cell_scale;
 } sr_tuning;
 
 int sr_set_tuning(sr_ctx *ctx, const sr_tuning *t);
 int sr_get_tuning(const sr_ctx *ctx, sr_tuning *t);
+
+/* ---- Precision form: split (cell + offset) coordinates ----------------- */
+
+/* A coordinate x of a PERIODIC box meshed into dims = floor(len/cell) chaining
+ * cells of width h = len/dims is held as its cell c = floor(x / h) (FP64) and
+ * the float32 offset o = fl32(x - c h) in [0, h).  The three cell indices
+ * are packed into one int32, cx | cy << 10 | cz << 20 (dims <= 1023 per
+ * axis).  Offsets carry rounding of ulp(h) instead of ulp(len), and the pair
+ * loop differences them without forming global coordinates, so float32
+ * forces track float64 master positions more closely than global float32
+ * coordinates can. */
+
+/* float64 positions (device double[n], 0 <= x < len) -> split coordinates
+ * (device int32 cell3[n], float ox/oy/oz[n]).  Out-of-range input sets the
+ * device status (SR_ERANGE at sr_sync). */
+int sr_split_from_f64(sr_ctx *ctx, const double *x, const double *y, const double *z, int64_t n,
+                      const sr_box *box, double cell, int32_t *cell3, float *ox, float *oy,
+                      float *oz);
+
+/* Split coordinates -> float64 positions in [0, len). */
+int sr_split_to_f64(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
+                    const float *oz, int64_t n, const sr_box *box, double cell, double *x,
+                    double *y, double *z);
+
+/* sr_force (Eq. (force), Sec. 3.1) on split coordinates: the same sum, with
+ * every separation formed as (o_j + cell-offset shift) - o_i in float32.
+ * Periodic boxes only; the x sub-cell count is min(tuning xsplit, 3).  An
+ * offset outside [0, 1.0001 h] or a cell index out of range sets the device
+ * status. */
+int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
+                   const float *oz, const float *mass, int64_t n, const sr_box *box, double cell,
+                   float r_max, float eps, const float poly[6], float *ax, float *ay, float *az,
+                   double *momentum3);
+
+/* ---- Batched form: many independent boxes per pass -------------------- */
+
+/* One box of a batch: device float32 inputs and outputs of its own, its own
+ * geometry and chaining cell.  Boxes never interact. */
+typedef struct sr_batch_box {
+    const float *x, *y, *z, *mass;
+    int64_t n;
+    sr_box box;
+    double cell;
+    float *ax, *ay, *az;
+} sr_batch_box;
+
+typedef struct sr_plan sr_plan;
+
+/* A plan evaluates Eq. (force) for all boxes of a batch in one pass: one
+ * segmented binning over the concatenated cell space, one pair-loop launch
+ * over every box's work items (longest first), and per-box FP64 momentum.
+ * (The paper's GPU design makes independent blocks the unit of work, Sec.
+ * 3.3; here a batch of boxes is one launch.)
+ *   boxes      : nboxes descriptors (HOST array, copied; device pointers
+ *                inside must stay valid for the plan's lifetime).  Each box
+ *                obeys the sr_force rules; total particles <= 2^31 - 1.
+ *   r_max, eps, poly : as sr_force, shared by all boxes.
+ *   momentum   : optional device double[3 * nboxes]; box b's sum_i m_i a_i
+ *                lands in momentum[3b .. 3b+2].
+ * The plan owns its scratch (sized for every tuning) and its descriptor
+ * table; creation waits for the upload.  Each box's accelerations are
+ * bitwise those of sr_force on that box alone with the same sr_tuning.
+ * Errors: SR_EINVAL (a bad box, with its index in sr_last_error),
+ * SR_ENOMEM, SR_EDEVICE. */
+int sr_plan_create(sr_ctx *ctx, const sr_batch_box *boxes, int nboxes, float r_max, float eps,
+                   const float poly[6], double *momentum, sr_plan **out);
+
+/* Change the plan's tuning (xsplit, order, persistent, cell_scale >= 1);
+ * re-uploads the descriptors (waits) and drops a captured graph.
+ * SR_EINVAL if some box is invalid at that cell_scale. */
+int sr_plan_set_tuning(sr_plan *plan, const sr_tuning *t);
+int sr_plan_get_tuning(const sr_plan *plan, sr_tuning *t);
+
+/* Enqueue one pass on the plan's stream (the context's stream, or a stream
+ * of the plan's own when the context uses the legacy default stream). */
+int sr_plan_run(sr_plan *plan);
+
+/* Record one pass into a HIP graph (no allocation, no memset nodes, no host
+ * synchronisation inside); sr_plan_launch then replays it.  The graph reads
+ * the boxes' current input buffers at every replay. */
+int sr_plan_capture(sr_plan *plan);
+
+/* Replay the captured graph (captures first if needed). */
+int sr_plan_launch(sr_plan *plan);
+
+/* Project autotuner: times `reps` passes (after one warm-up) of every
+ * candidate tuning -- xsplit in {1, 2, 3}, order in {0, 1}, persistent in
+ * {0, 1}, cell_scale in {1, 1.25} -- with HIP events, keeps the fastest
+ * (median), and leaves the plan set to it.  best / best_ms are HOST
+ * pointers (either may be NULL).  Waits for the stream. */
+int sr_plan_autotune(sr_plan *plan, int reps, sr_tuning *best, double *best_ms);
+
+/* Wait for the plan's stream and free everything the plan owns. */
+int sr_plan_destroy(sr_plan *plan);
+
+/* ---- Serving form: continuous batching of time-stepping requests ------- */
+
+/* A request evolves one periodic cube of n particles for `steps`
+ * stream-kick-stream steps (Sec. 2.5: x += v dt/2; a = f_SR; v += a dt;
+ * x += v dt/2) with the short-range force only.  State stays resident in
+ * HBM in split coordinates (cell + float32 offset, velocity float32) from
+ * admission to completion. */
+typedef struct sr_request {
+    int64_t n;
+    double len;                  /* cube side; must be exact in float32 */
+    int32_t steps;               /* >= 1 */
+    float dt;
+    const double *x, *y, *z;     /* HOST float64 initial positions in [0, len) */
+    const float *vx, *vy, *vz;   /* HOST initial velocities */
+    const float *mass;           /* HOST masses */
+    double *out_x, *out_y, *out_z;   /* HOST final positions (written at completion) */
+    float *out_vx, *out_vy, *out_vz; /* HOST final velocities */
+} sr_request;
+
+typedef struct sr_server_config {
+    size_t hbm_budget;     /* bytes: half for resident state, half for pass scratch */
+    int32_t max_slots;     /* requests active at once (>= 1) */
+    float r_max, eps;
+    float poly[6];
+    double cell;           /* chaining cell of every request's box */
+    sr_tuning tuning;      /* xsplit (<= 3 used), order, persistent; fixed for the server */
+} sr_server_config;
+
+typedef struct sr_server_info {
+    int64_t queued, active, draining, completed;
+    size_t state_bytes_in_use, state_bytes_high_water, state_bytes_capacity;
+    size_t scratch_bytes_capacity;
+    int64_t ticks;
+} sr_server_info;
+
+typedef struct sr_server sr_server;
+
+/* Create a server on the context's device and stream; allocates the budget
+ * up front (one state pool, one scratch arena).  Errors: SR_EINVAL,
+ * SR_ENOMEM. */
+int sr_server_create(sr_ctx *ctx, const sr_server_config *cfg, sr_server **out);
+
+/* Queue a request (FIFO).  The host arrays it points to must stay valid until
+ * the request completes (outputs should be pinned host memory so that the
+ * result copies stay asynchronous).  *id receives the request id.
+ * SR_EINVAL for an invalid request, SR_EBUSY if the request could never fit
+ * the budget. */
+int sr_server_submit(sr_server *srv, const sr_request *req, int64_t *id);
+
+/* One tick: admit queued requests in order while slots, state memory and
+ * scratch allow; advance every active request by one step in a single
+ * batched pass (stream, binning, pair loop, kick + stream); start the result
+ * copies of requests that finished.  Only enqueues work, except that it may
+ * wait for the tick that used the same descriptor buffer R ticks ago.
+ * *active (HOST, may be NULL) receives the number of requests stepped. */
+int sr_server_tick(sr_server *srv, int *active);
+
+/* Ids of requests whose results have landed in their host outputs since the
+ * last poll (HOST array of capacity cap; *n receives the count).  Frees their
+ * state memory. */
+int sr_server_poll(sr_server *srv, int64_t *ids, int cap, int *n);
+
+/* Drop a queued or active request; its memory is freed once the device no
+ * longer uses it.  Other requests are unaffected.  SR_EINVAL if unknown or
+ * already finished. */
+int sr_server_cancel(sr_server *srv, int64_t id);
+
+int sr_server_info_get(const sr_server *srv, sr_server_info *info);
+
+/* Wait for all work and free the server (requests still queued or active
+ * are dropped). */
+int sr_server_destroy(sr_server *srv);
 
 /* Device-side timing of sr_force (a measurement helper).  While enabled,
  * each sr_force call records HIP events on the context's stream: one before

@@ -14,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sr_ctx.cpp", "sr_bin.hip", "sr_force.hip", "sr_batch.hip", "sr_serve.cpp"]
+SOURCES = ["sr_ctx.cpp", "sr_bin.hip", "sr_force.hip", "sr_split.hip", "sr_plan.cpp",
+           "sr_serve.cpp"]
 
 # Device flags: gfx950 only; explicit fmaf everywhere, so no implicit
 # contraction; packed FP32 instructions are switched off in code generation.

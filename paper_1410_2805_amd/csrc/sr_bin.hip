@@ -15,6 +15,8 @@
 //              to k_segsort_large (one block, LDS-sorted runs merged by rank).
 //              The same pass gathers the sorted float4 (x, y, z, m) copy and
 //              counts force work items per cell.
+// All kernels work on a batch of boxes whose particles and cells are numbered
+// consecutively; one box is a batch of one.
 #include <climits>
 
 #include "sr_internal.h"
@@ -74,35 +76,56 @@ __global__ void k_fill(int *__restrict__ p, int value, int64_t count)
         p[i] = value;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cellid(const float *__restrict__ x,
-                                                   const float *__restrict__ y,
-                                                   const float *__restrict__ z, int n, Geom g,
-                                                   int *__restrict__ cid, int *__restrict__ slot,
+__global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ cid,
+                                                   int *__restrict__ slot,
                                                    int *__restrict__ count, int *__restrict__ status)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const bool live = i < n;
+    const bool live = i < B.ntot;
     int id = 0;
     if (live) {
-        const float p[3] = {x[i], y[i], z[i]};
+        const BoxDesc &d = box_at(B, find_box(B.pstart, B.nb, i));
+        const int li = i - d.pbase;
+        const float p[3] = {d.x[li], d.y[li], d.z[li]};
+        const Geom &g = d.g;
         int c[3];
         bool bad = false;
+        if (g.split) {
+            // chaining cell from cell3; the x sub-cell from the offset
+            const int packed = d.cell3[li];
+            const int cc[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
+            const int per[3] = {g.hx, 1, 1};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double v = (double)p[d];
-            if (!(v >= 0.0 && v < g.len[d])) {  // also catches NaN
-                bad = true;
-                c[d] = 0;
-            } else {
-                double t = floor(v * g.inv[d]);
-                int ci = (int)t;
-                c[d] = ci < g.nc[d] - 1 ? ci : g.nc[d] - 1;
+            for (int k = 0; k < 3; ++k) {
+                const double v = (double)p[k];
+                const int ncc = g.nc[k] / per[k];
+                if (!(v >= 0.0 && v <= 1.0001 * g.w[k] * per[k]) || cc[k] >= ncc) {
+                    bad = true;
+                    c[k] = 0;
+                } else {
+                    int sub = (int)floor(v * g.inv[k]);
+                    sub = sub < per[k] - 1 ? sub : per[k] - 1;
+                    c[k] = cc[k] * per[k] + sub;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double v = (double)p[k];
+                if (!(v >= 0.0 && v < g.len[k])) {  // also catches NaN
+                    bad = true;
+                    c[k] = 0;
+                } else {
+                    double t = floor(v * g.inv[k]);
+                    int ci = (int)t;
+                    c[k] = ci < g.nc[k] - 1 ? ci : g.nc[k] - 1;
+                }
             }
         }
         if (bad)
             atomicOr(status, 1);
-        id = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+        id = d.cbase + c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
         cid[i] = id;
     }
     // Spatially ordered input puts many lanes of a wavefront in one cell:
@@ -230,21 +253,26 @@ __device__ void lds_bitonic(int *buf, int P, int lane)
     }
 }
 
-__device__ __forceinline__ void gather_one(float4 *sorted, int k, int src, const float *x,
-                                           const float *y, const float *z, const float *m)
+__device__ __forceinline__ float4 gather_one(const BoxDesc &d, int v)
 {
-    sorted[k] = make_float4(x[src], y[src], z[src], m[src]);
+    const int li = v - d.pbase;
+    float x = d.x[li];
+    if (d.g.split && d.g.hx > 1) {
+        // offset from the x sub-cell corner (same sub-cell rule as k_cellid)
+        const double o = (double)x;
+        int sub = (int)floor(o * d.g.inv[0]);
+        sub = sub < d.g.hx - 1 ? sub : d.g.hx - 1;
+        sub = sub > 0 ? sub : 0;
+        x = (float)(o - (double)sub * d.g.w[0]);
+    }
+    return make_float4(x, d.y[li], d.z[li], d.m[li]);
 }
 
 // One wavefront per cell.
-__global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offsets, int ncell,
+__global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restrict__ offsets,
                                                     int *__restrict__ perm,
                                                     int *__restrict__ large_list,
                                                     int *__restrict__ large_count,
-                                                    const float *__restrict__ x,
-                                                    const float *__restrict__ y,
-                                                    const float *__restrict__ z,
-                                                    const float *__restrict__ m,
                                                     float4 *__restrict__ sorted,
                                                     int *__restrict__ chunk_count,
                                                     int *__restrict__ mass_mixed)
@@ -253,12 +281,13 @@ __global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offs
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int cell = blockIdx.x * (kBlock / 64) + wid;
-    if (cell >= ncell)
+    if (cell >= B.ctot)
         return;
     const int b = offsets[cell];
     const int len = offsets[cell + 1] - b;
     if (chunk_count && lane == 0)
         chunk_count[cell] = chunks_for(len);
+    const int box = sorted ? find_box(B.cstart, B.nb, cell) : 0;
     if (len <= 64) {
         int v = lane < len ? perm[b + lane] : INT_MAX;
         v = bitonic64(v, lane);
@@ -266,12 +295,14 @@ __global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offs
         if (lane < len) {
             perm[b + lane] = v;
             if (sorted) {
-                gather_one(sorted, b + lane, v, x, y, z, m);
-                mixed = m[v] != m[0];
+                const BoxDesc &d = box_at(B, box);
+                const float4 q = gather_one(d, v);
+                sorted[b + lane] = q;
+                mixed = q.w != d.m[0];
             }
         }
         if (__any(mixed) && lane == 0)
-            atomicOr(mass_mixed, 1);
+            atomicOr(&mass_mixed[box], 1);
     } else if (len <= kLargeCell) {
         int P = 128;
         while (P < len)
@@ -286,12 +317,14 @@ __global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offs
             int v = sb[t];
             perm[b + t] = v;
             if (sorted) {
-                gather_one(sorted, b + t, v, x, y, z, m);
-                mixed = mixed || m[v] != m[0];
+                const BoxDesc &d = box_at(B, box);
+                const float4 q = gather_one(d, v);
+                sorted[b + t] = q;
+                mixed = mixed || q.w != d.m[0];
             }
         }
         if (__any(mixed) && lane == 0)
-            atomicOr(mass_mixed, 1);
+            atomicOr(&mass_mixed[box], 1);
     } else if (lane == 0) {
         int k = atomicAdd(large_count, 1);
         large_list[k] = cell;
@@ -301,15 +334,12 @@ __global__ __launch_bounds__(kBlock) void k_segsort(const int *__restrict__ offs
 // Block-level sort of one large cell: LDS-sorted runs of kLargeCell, then
 // merge rounds in which every element finds its output slot from its rank in
 // the partner run (values are distinct original indices).
-__global__ __launch_bounds__(kBlock) void k_segsort_large(const int *__restrict__ offsets,
+__global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
+                                                          const int *__restrict__ offsets,
                                                           int *__restrict__ perm,
                                                           int *__restrict__ tmp,
                                                           const int *__restrict__ large_list,
                                                           const int *__restrict__ large_count,
-                                                          const float *__restrict__ x,
-                                                          const float *__restrict__ y,
-                                                          const float *__restrict__ z,
-                                                          const float *__restrict__ m,
                                                           float4 *__restrict__ sorted,
                                                           int *__restrict__ mass_mixed)
 {
@@ -384,14 +414,16 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(const int *__restrict_
             __syncthreads();
         }
         if (sorted) {
+            const int box = find_box(B.cstart, B.nb, cell);
+            const BoxDesc &d = box_at(B, box);
             bool mixed = false;
             for (int e = threadIdx.x; e < len; e += kBlock) {
-                const int v = perm[b + e];
-                gather_one(sorted, b + e, v, x, y, z, m);
-                mixed = mixed || m[v] != m[0];
+                const float4 q = gather_one(d, perm[b + e]);
+                sorted[b + e] = q;
+                mixed = mixed || q.w != d.m[0];
             }
             if (mixed)
-                atomicOr(mass_mixed, 1);
+                atomicOr(&mass_mixed[box], 1);
         }
         __syncthreads();
     }
@@ -431,38 +463,39 @@ int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out)
     return sr_check_launch(ctx, "scan");
 }
 
-void bin_layout(Bump &b, int64_t n, const Geom &g, BinScratch &s)
+void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
 {
-    size_t nn = (size_t)(n > 0 ? n : 1);
+    size_t nn = (size_t)(ntot > 0 ? ntot : 1);
     s.cid = b.take<int>(nn);
     s.slot = b.take<int>(nn);
-    s.count = b.take<int>((size_t)g.ncell);
-    scan_layout(b, g.ncell, &s.scan_part);
+    s.count = b.take<int>((size_t)ctot);
+    scan_layout(b, (int)ctot, &s.scan_part);
     s.tmp = b.take<int>(nn);
     s.large_list = b.take<int>(nn / (kLargeCell + 1) + 1);
     s.large_count = b.take<int>(1);
-    s.mass_mixed = b.take<int>(1);
+    s.mass_mixed = b.take<int>((size_t)(nb > 0 ? nb : 1));
 }
 
-// Enqueue the whole binning pass.  sorted/m and chunk_count may be NULL.
-int bin_enqueue(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *m,
-                int n, const Geom &g, const BinScratch &s, int *offsets, int *perm,
+// Enqueue the whole binning pass.  sorted and chunk_count may be NULL (then
+// no gather and no item counts).
+int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, int *perm,
                 float4 *sorted, int *chunk_count)
 {
     int rc;
-    if ((rc = fill_enqueue(ctx, s.count, 0, g.ncell)))
+    if ((rc = fill_enqueue(ctx, s.count, 0, B.ctot)))
         return rc;
     if ((rc = fill_enqueue(ctx, s.large_count, 0, 1)))
         return rc;
-    if ((rc = fill_enqueue(ctx, s.mass_mixed, 0, 1)))
+    if ((rc = fill_enqueue(ctx, s.mass_mixed, 0, B.nb)))
         return rc;
+    const int n = B.ntot;
     if (n > 0) {
         hipLaunchKernelGGL(k_cellid, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
-                           x, y, z, n, g, s.cid, s.slot, s.count, ctx->status);
+                           B, s.cid, s.slot, s.count, ctx->status);
         if ((rc = sr_check_launch(ctx, "k_cellid")))
             return rc;
     }
-    if ((rc = scan_enqueue(ctx, s.count, g.ncell, s.scan_part, offsets)))
+    if ((rc = scan_enqueue(ctx, s.count, B.ctot, s.scan_part, offsets)))
         return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
@@ -470,17 +503,16 @@ int bin_enqueue(sr_ctx *ctx, const float *x, const float *y, const float *z, con
         if ((rc = sr_check_launch(ctx, "k_scatter")))
             return rc;
     }
-    hipLaunchKernelGGL(k_segsort, dim3(blocks_for(g.ncell, kBlock / 64)), dim3(kBlock), 0,
-                       ctx->stream, offsets, g.ncell, perm, s.large_list, s.large_count, x, y, z,
-                       m, sorted, chunk_count, s.mass_mixed);
+    hipLaunchKernelGGL(k_segsort, dim3(blocks_for(B.ctot, kBlock / 64)), dim3(kBlock), 0,
+                       ctx->stream, B, offsets, perm, s.large_list, s.large_count, sorted,
+                       chunk_count, s.mass_mixed);
     if ((rc = sr_check_launch(ctx, "k_segsort")))
         return rc;
     if (n > kLargeCell) {
         int max_large = n / (kLargeCell + 1) + 1;
         int grid = max_large < 2048 ? max_large : 2048;
-        hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kBlock), 0, ctx->stream, offsets,
-                           perm, s.tmp, s.large_list, s.large_count, x, y, z, m, sorted,
-                           s.mass_mixed);
+        hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kBlock), 0, ctx->stream, B, offsets,
+                           perm, s.tmp, s.large_list, s.large_count, sorted, s.mass_mixed);
         if ((rc = sr_check_launch(ctx, "k_segsort_large")))
             return rc;
     }
@@ -497,18 +529,25 @@ extern "C" int sr_bin(sr_ctx *ctx, const float *x, const float *y, const float *
         return sr_fail(ctx, SR_EINVAL, "n=%lld out of range", (long long)n);
     if (!cell_offsets || (n > 0 && (!x || !y || !z || !perm)))
         return sr_fail(ctx, SR_EINVAL, "NULL pointer");
-    Geom g;
-    int rc = sr_make_geom(ctx, box, cell, &g);
+    Batch B{};
+    int rc = sr_make_geom(ctx, box, cell, &B.one.g);
     if (rc)
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    B.nb = 1;
+    B.ntot = (int)n;
+    B.ctot = B.one.g.ncell;
+    B.one.n = (int)n;
+    B.one.x = x;
+    B.one.y = y;
+    B.one.z = z;
     Bump sz{nullptr, 0, 0};
     BinScratch s;
-    bin_layout(sz, n, g, s);
+    bin_layout(sz, n, B.ctot, 1, s);
     if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
-    bin_layout(b, n, g, s);
-    return bin_enqueue(ctx, x, y, z, nullptr, (int)n, g, s, cell_offsets, perm, nullptr, nullptr);
+    bin_layout(b, n, B.ctot, 1, s);
+    return bin_enqueue(ctx, B, s, cell_offsets, perm, nullptr, nullptr);
 }

@@ -70,11 +70,13 @@ int sr_make_geom(sr_ctx *ctx, const sr_box *box, double cell, Geom *g, int xspli
         g->inv[d] = (double)dims[d] / box->len[d];
         g->lenf[d] = (float)box->len[d];
         g->nc[d] = dims[d];
+        g->w[d] = box->len[d] / (double)dims[d];
         if ((double)g->lenf[d] != box->len[d])
             return sr_fail(ctx, SR_EINVAL, "box side %g is not exactly representable in float32",
                            box->len[d]);
     }
     g->ncell = (int)nc;
+    g->split = 0;
     g->periodic = box->periodic ? 1 : 0;
     g->skin = box->periodic ? 0.0 : box->skin;
     if (!box->periodic && !(box->skin >= 0.0))
@@ -195,7 +197,11 @@ extern "C" int sr_set_tuning(sr_ctx *ctx, const sr_tuning *t)
         return SR_EINVAL;
     if (t->xsplit < 1 || t->xsplit > kMaxXsplit)
         return sr_fail(ctx, SR_EINVAL, "xsplit must be in [1, %d]", kMaxXsplit);
+    if (t->order < 0 || t->order > 1 || t->persistent < 0 || t->persistent > 1)
+        return sr_fail(ctx, SR_EINVAL, "order and persistent must be 0 or 1");
     ctx->xsplit = t->xsplit;
+    ctx->order = t->order;
+    ctx->persistent = t->persistent;
     return SR_OK;
 }
 
@@ -204,7 +210,9 @@ extern "C" int sr_get_tuning(const sr_ctx *ctx, sr_tuning *t)
     if (!ctx || !t)
         return SR_EINVAL;
     t->xsplit = ctx->xsplit;
-    t->_reserved[0] = t->_reserved[1] = t->_reserved[2] = 0;
+    t->order = ctx->order;
+    t->persistent = ctx->persistent;
+    t->cell_scale = 1.0f;
     return SR_OK;
 }
 

@@ -17,6 +17,12 @@
 // Periodic images are made exact: a target in the last cell layer of an axis
 // works in a frame shifted by -L there, so every image shift is 0 or -L and is
 // only ever applied to coordinates >= L/2, where subtracting L is exact.
+//
+// Everything runs on a batch of boxes (one box = a batch of one): a work item
+// carries its box, whose geometry, inputs and outputs it reads from the
+// batch descriptor.  Items may be ordered by decreasing cost bucket (longest
+// first) and are either one workgroup each or pulled from a counter by
+// persistent workgroups.
 #include <climits>
 #include <cmath>
 
@@ -27,10 +33,14 @@ namespace {
 constexpr int kTile = 256;       // sources per LDS tile (4 KiB)
 constexpr float kFar = 1.0e6f;   // padding source far outside any box, mass 0
 
+// Source pieces of one target cell: at most 18 (9 rows, each split where it
+// wraps) in global coordinates, at most 63 (one per cell) in split
+// coordinates.  pbeg[npiece] = all sources; unused pieces are empty.
+constexpr int kMaxPieces = 64;
 struct Stencil {
-    int pbeg[19];      // prefix of piece lengths; pbeg[18] = all sources
-    int psrc[18];      // first sorted slot of each piece
-    float4 psh[18];    // image shift of each piece
+    int pbeg[kMaxPieces + 1];  // prefix of piece lengths
+    int psrc[kMaxPieces];      // first sorted slot of each piece
+    float4 psh[kMaxPieces];    // shift added to the piece's coordinates
 };
 
 __device__ __forceinline__ int wave_exclusive_scan(int v, int lane, int *total)
@@ -47,13 +57,31 @@ __device__ __forceinline__ int wave_exclusive_scan(int v, int lane, int *total)
 }
 
 // Builds the source pieces of target cell (cx, cy, cz) into st (all lanes
-// call; lanes < 18 each own one piece slot: row r = lane/2, half = lane%2).
+// call).  Global coordinates: lanes < 18 each own one piece slot, row r =
+// lane/2, half = lane%2, the shift is the periodic image shift.  Split
+// coordinates: lanes < 9 (2 hx + 1) each own one cell of the stencil and the
+// shift is the cell's offset from the target cell, (dx w0, dy w1, dz w2), so
+// coordinates stay cell-relative and periodic wrap needs no shift at all.
 __device__ void build_stencil(Stencil &st, const int *__restrict__ offsets, const Geom &g, int cx,
                               int cy, int cz, const float F[3], int lane)
 {
     int len = 0, src = 0;
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    if (lane < 18) {
+    const int W = 2 * g.hx + 1;
+    if (g.split && lane < 9 * W) {
+        const int r = lane / W, k = lane - r * W;
+        const int dx = k - g.hx, dy = r % 3 - 1, dz = r / 3 - 1;
+        int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+        nx = nx < 0 ? nx + g.nc[0] : (nx >= g.nc[0] ? nx - g.nc[0] : nx);
+        ny = ny < 0 ? ny + g.nc[1] : (ny >= g.nc[1] ? ny - g.nc[1] : ny);
+        nz = nz < 0 ? nz + g.nc[2] : (nz >= g.nc[2] ? nz - g.nc[2] : nz);
+        const int id = nx + g.nc[0] * (ny + g.nc[1] * nz);
+        src = offsets[id];
+        len = offsets[id + 1] - src;
+        sx = (float)((double)dx * g.w[0]);
+        sy = (float)((double)dy * g.w[1]);
+        sz = (float)((double)dz * g.w[2]);
+    } else if (!g.split && lane < 18) {
         const int r = lane >> 1, half = lane & 1;
         const int dy = r % 3 - 1, dz = r / 3 - 1;
         int ny = cy + dy, nz = cz + dz;
@@ -99,13 +127,11 @@ __device__ void build_stencil(Stencil &st, const int *__restrict__ offsets, cons
     }
     int total;
     int beg = wave_exclusive_scan(len, lane, &total);
-    if (lane < 18) {
-        st.pbeg[lane] = beg;
-        st.psrc[lane] = src;
-        st.psh[lane] = make_float4(sx, sy, sz, 0.f);
-    }
+    st.pbeg[lane] = beg;
+    st.psrc[lane] = src;
+    st.psh[lane] = make_float4(sx, sy, sz, 0.f);
     if (lane == 0)
-        st.pbeg[18] = total;
+        st.pbeg[kMaxPieces] = total;
 }
 
 // A target whose stencil wraps past the upper face of an axis works in a
@@ -117,7 +143,7 @@ __device__ __forceinline__ void frame_shift(const Geom &g, const int cc[3], floa
     const int h[3] = {g.hx, 1, 1};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        F[d] = (g.periodic && cc[d] + h[d] >= g.nc[d]) ? -g.lenf[d] : 0.f;
+        F[d] = (g.periodic && !g.split && cc[d] + h[d] >= g.nc[d]) ? -g.lenf[d] : 0.f;
 }
 
 __device__ __forceinline__ void decode_cell(int cell, const Geom &g, int &cx, int &cy, int &cz)
@@ -195,37 +221,28 @@ __device__ __forceinline__ void pair_tile(const float4 *src, int cnt, float xi, 
     }
 }
 
-// One wavefront per work item (a chunk of nt <= 64 targets of one cell).
-// Lane L serves target t = L mod nt in group part = L / nt; the S groups
-// split each staged tile into S contiguous slices.
-__global__ __launch_bounds__(64) void k_force(const int4 *__restrict__ items,
-                                              const int *__restrict__ n_items,
-                                              const float4 *__restrict__ sorted,
-                                              const int *__restrict__ offsets,
-                                              const int *__restrict__ perm,
-                                              const int *__restrict__ mass_mixed, Geom g,
-                                              ForceParams fp, float *__restrict__ ax,
-                                              float *__restrict__ ay, float *__restrict__ az)
+// Item layout: {cell (global), first sorted slot, targets, S | box << 5}.
+__device__ __forceinline__ int item_split(const int4 &it) { return it.w & 31; }
+__device__ __forceinline__ int item_box(const int4 &it) { return it.w >> 5; }
+
+// The pair loop of one work item by one wavefront (tile, st, red: LDS).
+__device__ __forceinline__ void process_item(const Batch &B, const int4 item,
+                                             const float4 *__restrict__ sorted,
+                                             const int *__restrict__ offsets,
+                                             const int *__restrict__ perm,
+                                             const int *__restrict__ mass_mixed,
+                                             const ForceParams &fp, float4 *tile, Stencil &st,
+                                             int lane)
 {
-    __shared__ float4 tile[kTile + 4 * kMaxSplit];
-    __shared__ Stencil st;
-    const int lane = threadIdx.x;
-    // Workgroups are dealt to the 8 XCDs round-robin; give XCD k the k-th
-    // contiguous eighth of the items so that neighbouring cells, which share
-    // most of their sources, meet in the same L2.
-    const int nitems = *n_items;
-    const int per = (nitems + 7) >> 3;
-    const int it = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if ((int)(blockIdx.x >> 3) >= per || it >= nitems)
-        return;
-    const int4 item = items[it];
-    const int cell = item.x, kb = item.y, nt = item.z, S = item.w;
+    const int kb = item.y, nt = item.z, S = item_split(item), box = item_box(item);
+    const BoxDesc &d = box_at(B, box);
+    const Geom &g = d.g;
     int cx, cy, cz;
-    decode_cell(cell, g, cx, cy, cz);
+    decode_cell(item.x - d.cbase, g, cx, cy, cz);
     const int cc[3] = {cx, cy, cz};
     float F[3];
     frame_shift(g, cc, F);
-    build_stencil(st, offsets, g, cx, cy, cz, F, lane);
+    build_stencil(st, offsets + d.cbase, g, cx, cy, cz, F, lane);
 
     const int part = lane / nt;
     const int t = lane - part * nt;
@@ -233,12 +250,12 @@ __global__ __launch_bounds__(64) void k_force(const int4 *__restrict__ items,
     const float4 pt = sorted[kb + t];
     const bool pas = is_passive(pt, g);
     const float xi = pt.x + F[0], yi = pt.y + F[1], zi = pt.z + F[2];
-    const bool uniform = *mass_mixed == 0;
+    const bool uniform = mass_mixed[box] == 0;
     __syncthreads();
 
     float acx = 0.f, acy = 0.f, acz = 0.f;
     if (__any(has_target && !pas)) {
-        const int total = st.pbeg[18];
+        const int total = st.pbeg[kMaxPieces];
         const int quantum = 4 * S;
         int p = 0;
         for (int g0 = 0; g0 < total; g0 += kTile) {
@@ -265,53 +282,109 @@ __global__ __launch_bounds__(64) void k_force(const int4 *__restrict__ items,
         }
     }
     // add the S group sums of each target in group order
-    float4 *red = tile;
-    red[lane] = make_float4(acx, acy, acz, 0.f);
+    tile[lane] = make_float4(acx, acy, acz, 0.f);
     __syncthreads();
     if (part == 0) {
         for (int q = 1; q < S; ++q) {
-            const float4 o = red[t + q * nt];
+            const float4 o = tile[t + q * nt];
             acx += o.x;
             acy += o.y;
             acz += o.z;
         }
-        const int orig = perm[kb + t];
-        ax[orig] = pas ? 0.f : acx;
-        ay[orig] = pas ? 0.f : acy;
-        az[orig] = pas ? 0.f : acz;
+        const int orig = perm[kb + t] - d.pbase;
+        d.ax[orig] = pas ? 0.f : acx;
+        d.ay[orig] = pas ? 0.f : acy;
+        d.az[orig] = pas ? 0.f : acz;
+    }
+    __syncthreads();  // the tile is reused by the next item
+}
+
+// Position in the item order served by workgroup b: workgroups are dealt to
+// the 8 XCDs round-robin, and XCD k serves the chunks of 64 consecutive
+// items k, k + 8, k + 16, ..., so each XCD sees the same mix of costs and
+// neighbouring cells (shared sources) meet in one L2.  A bijection on
+// [0, grid) for grid a multiple of 512.
+__device__ __forceinline__ int item_position(int b)
+{
+    const int xcd = b & 7, j = b >> 3;
+    return ((j >> 6) * 8 + xcd) * 64 + (j & 63);
+}
+
+__global__ __launch_bounds__(64) void k_force(Batch B, const int4 *__restrict__ items,
+                                              const int *__restrict__ n_items,
+                                              const float4 *__restrict__ sorted,
+                                              const int *__restrict__ offsets,
+                                              const int *__restrict__ perm,
+                                              const int *__restrict__ mass_mixed, ForceParams fp)
+{
+    __shared__ float4 tile[kTile + 4 * kMaxSplit];
+    __shared__ Stencil st;
+    const int pos = item_position(blockIdx.x);
+    if (pos >= *n_items)
+        return;
+    process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st, threadIdx.x);
+}
+
+// Persistent variant: a fixed grid of workgroups takes items in order from a
+// counter until none are left (every workgroup reaches the exit).
+__global__ __launch_bounds__(64) void k_force_persistent(Batch B, const int4 *__restrict__ items,
+                                                         const int *__restrict__ n_items,
+                                                         const float4 *__restrict__ sorted,
+                                                         const int *__restrict__ offsets,
+                                                         const int *__restrict__ perm,
+                                                         const int *__restrict__ mass_mixed,
+                                                         ForceParams fp, int *__restrict__ queue)
+{
+    __shared__ float4 tile[kTile + 4 * kMaxSplit];
+    __shared__ Stencil st;
+    __shared__ int next;
+    const int n = *n_items;
+    for (;;) {
+        if (threadIdx.x == 0)
+            next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int pos = next;
+        __syncthreads();
+        if (pos >= n)
+            break;
+        process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st,
+                     threadIdx.x);
     }
 }
 
-// Useful-pair and candidate counts with the same stencil and cutoff test.
-__global__ __launch_bounds__(64) void k_pair_stats(const int4 *__restrict__ items,
+// Useful-pair and candidate counts with the same stencil and cutoff test
+// (one box).
+__global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restrict__ items,
                                                    const int *__restrict__ n_items,
                                                    const float4 *__restrict__ sorted,
                                                    const int *__restrict__ offsets,
-                                                   const int *__restrict__ perm, Geom g,
-                                                   ForceParams fp, int *__restrict__ per_target,
+                                                   const int *__restrict__ perm, ForceParams fp,
+                                                   int *__restrict__ per_target,
                                                    unsigned long long *__restrict__ stats)
 {
-    __shared__ float4 tile[kTile];
+    __shared__ float4 tile[kTile + 4 * kMaxSplit];
     __shared__ Stencil st;
     const int lane = threadIdx.x;
     const int it = blockIdx.x;
     if (it >= *n_items)
         return;
     const int4 item = items[it];
-    const int cell = item.x, kb = item.y, nt = item.z;
+    const int kb = item.y, nt = item.z;
+    const BoxDesc &d = box_at(B, item_box(item));
+    const Geom &g = d.g;
     int cx, cy, cz;
-    decode_cell(cell, g, cx, cy, cz);
+    decode_cell(item.x - d.cbase, g, cx, cy, cz);
     const int cc[3] = {cx, cy, cz};
     float F[3];
     frame_shift(g, cc, F);
-    build_stencil(st, offsets, g, cx, cy, cz, F, lane);
+    build_stencil(st, offsets + d.cbase, g, cx, cy, cz, F, lane);
     const bool has_target = lane < nt;
     const float4 pt = sorted[kb + (has_target ? lane : 0)];
     const bool pas = is_passive(pt, g);
     const bool act = has_target && !pas;
     const float xi = pt.x + F[0], yi = pt.y + F[1], zi = pt.z + F[2];
     __syncthreads();
-    const int total = st.pbeg[18];
+    const int total = st.pbeg[kMaxPieces];
     int cntu = 0;
     int p = 0;
     for (int g0 = 0; g0 < total; g0 += kTile) {
@@ -329,7 +402,7 @@ __global__ __launch_bounds__(64) void k_pair_stats(const int4 *__restrict__ item
     }
     cntu = act ? cntu - 1 : 0;  // the target itself is always in its stencil
     if (has_target && per_target)
-        per_target[perm[kb + lane]] = cntu;
+        per_target[perm[kb + lane] - d.pbase] = cntu;
     unsigned long long u = (unsigned long long)cntu;
     unsigned long long c = act ? (unsigned long long)total : 0ull;
     for (int o = 1; o < 64; o <<= 1) {
@@ -343,52 +416,149 @@ __global__ __launch_bounds__(64) void k_pair_stats(const int4 *__restrict__ item
 }
 
 // One thread per cell: the cell's targets split into chunk_count[c] nearly
-// equal chunks of at most kChunk.
-__global__ void k_items(const int *__restrict__ offsets, const int *__restrict__ item_off,
-                        int ncell, int4 *__restrict__ items)
+// equal chunks; each item also gets a cost bucket floor(log2(cost)) with
+// cost = stencil sources / S + 64 (wavefront iterations plus overhead).
+__global__ void k_items(Batch B, const int *__restrict__ offsets,
+                        const int *__restrict__ item_off, int4 *__restrict__ items,
+                        int *__restrict__ item_cost)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell)
+    if (c >= B.ctot)
         return;
+    const int q = item_off[c + 1] - item_off[c];
+    if (q == 0)
+        return;
+    const int box = find_box(B.cstart, B.nb, c);
+    const BoxDesc &d = box_at(B, box);
+    const Geom &g = d.g;
     const int b = offsets[c];
     const int len = offsets[c + 1] - b;
-    const int q = item_off[c + 1] - item_off[c];
+    // stencil size (same rows as build_stencil, without the shifts)
+    int cx, cy, cz;
+    decode_cell(c - d.cbase, g, cx, cy, cz);
+    const int *off = offsets + d.cbase;
+    long long src = 0;
+    for (int r = 0; r < 9; ++r) {
+        int ny = cy + r % 3 - 1, nz = cz + r / 3 - 1;
+        if (g.periodic) {
+            ny = ny < 0 ? ny + g.nc[1] : (ny >= g.nc[1] ? ny - g.nc[1] : ny);
+            nz = nz < 0 ? nz + g.nc[2] : (nz >= g.nc[2] ? nz - g.nc[2] : nz);
+        } else if (ny < 0 || ny >= g.nc[1] || nz < 0 || nz >= g.nc[2]) {
+            continue;
+        }
+        const int row = g.nc[0] * (ny + g.nc[1] * nz);
+        const int lo = cx - g.hx, hi = cx + g.hx, n0 = g.nc[0];
+        if (g.periodic) {
+            if (lo < 0)
+                src += (off[row + hi + 1] - off[row]) + (off[row + n0] - off[row + lo + n0]);
+            else if (hi >= n0)
+                src += (off[row + n0] - off[row + lo]) + (off[row + hi - n0 + 1] - off[row]);
+            else
+                src += off[row + hi + 1] - off[row + lo];
+        } else {
+            const int a = lo > 0 ? lo : 0, e = hi < n0 - 1 ? hi : n0 - 1;
+            src += off[row + e + 1] - off[row + a];
+        }
+    }
     for (int k = 0; k < q; ++k) {
         const int lo = (int)((long long)k * len / q);
         const int hi = (int)((long long)(k + 1) * len / q);
-        items[item_off[c] + k] = make_int4(c, b + lo, hi - lo, split_for(hi - lo));
+        const int S = split_for(hi - lo);
+        items[item_off[c] + k] = make_int4(c, b + lo, hi - lo, S | (box << 5));
+        const long long cost = src / S + 64;
+        item_cost[item_off[c] + k] = 63 - __clzll((unsigned long long)cost);
     }
 }
 
-constexpr int kRedBlocks = 256;
+// Stable counting sort of items by decreasing cost bucket (key = 31 - bucket):
+// per-block key histograms, a scan in key-major order, stable scatter.
+__global__ __launch_bounds__(256) void k_lpt_hist(const int *__restrict__ item_cost,
+                                                  const int *__restrict__ n_items, int nblk,
+                                                  int *__restrict__ hist)
+{
+    __shared__ int h[32];
+    if (threadIdx.x < 32)
+        h[threadIdx.x] = 0;
+    __syncthreads();
+    const int n = *n_items;
+    for (int k = 0; k < kLptBlock / 256; ++k) {
+        const int i = blockIdx.x * kLptBlock + k * 256 + threadIdx.x;
+        if (i < n)
+            atomicAdd(&h[31 - item_cost[i]], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32)
+        hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
 
-// FP64 sum_i m_i a_i: fixed per-thread ranges, fixed tree order.
-__global__ __launch_bounds__(256) void k_momentum_partial(const float *__restrict__ m,
-                                                          const float *__restrict__ ax,
-                                                          const float *__restrict__ ay,
-                                                          const float *__restrict__ az, int n,
-                                                          double *__restrict__ part)
+__global__ __launch_bounds__(256) void k_lpt_scatter(const int4 *__restrict__ items,
+                                                     const int *__restrict__ item_cost,
+                                                     const int *__restrict__ n_items, int nblk,
+                                                     const int *__restrict__ key_off,
+                                                     int4 *__restrict__ out)
+{
+    __shared__ int run[32];
+    __shared__ int wcnt[4][32];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x < 32)
+        run[threadIdx.x] = 0;
+    const int n = *n_items;
+    for (int k = 0; k < kLptBlock / 256; ++k) {
+        if (threadIdx.x < 128)
+            wcnt[threadIdx.x >> 5][threadIdx.x & 31] = 0;
+        __syncthreads();
+        const int i = blockIdx.x * kLptBlock + k * 256 + threadIdx.x;
+        const bool live = i < n;
+        const int key = live ? 31 - item_cost[i] : 0;
+        // lanes of this wavefront with the same key, by 5 ballots
+        unsigned long long same = __ballot(live);
+#pragma unroll
+        for (int bit = 0; bit < 5; ++bit) {
+            const unsigned long long v = __ballot(live && ((key >> bit) & 1));
+            same &= ((key >> bit) & 1) ? v : ~v;
+        }
+        const int rank = __popcll(same & ((1ull << lane) - 1ull));
+        if (live && rank == 0)
+            wcnt[wid][key] = __popcll(same);
+        __syncthreads();
+        if (live) {
+            int before = run[key];
+            for (int w = 0; w < wid; ++w)
+                before += wcnt[w][key];
+            out[key_off[key * nblk + blockIdx.x] + before + rank] = items[i];
+        }
+        __syncthreads();
+        if (threadIdx.x < 32)
+            run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] +
+                                wcnt[2][threadIdx.x] + wcnt[3][threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// FP64 sum_i m_i a_i per box: fixed per-thread ranges, fixed tree order.
+__global__ __launch_bounds__(256) void k_momentum_partial(Batch B, double *__restrict__ part)
 {
     __shared__ double sh[3][256];
+    const BoxDesc &d = box_at(B, blockIdx.y);
     double s[3] = {0.0, 0.0, 0.0};
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kRedBlocks * 256) {
-        const double mi = (double)m[i];
-        s[0] += mi * (double)ax[i];
-        s[1] += mi * (double)ay[i];
-        s[2] += mi * (double)az[i];
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < d.n; i += kRedBlocks * 256) {
+        const double mi = (double)d.m[i];
+        s[0] += mi * (double)d.ax[i];
+        s[1] += mi * (double)d.ay[i];
+        s[2] += mi * (double)d.az[i];
     }
-    for (int d = 0; d < 3; ++d)
-        sh[d][threadIdx.x] = s[d];
+    for (int k = 0; k < 3; ++k)
+        sh[k][threadIdx.x] = s[k];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
-            for (int d = 0; d < 3; ++d)
-                sh[d][threadIdx.x] += sh[d][threadIdx.x + w];
+            for (int k = 0; k < 3; ++k)
+                sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int d = 0; d < 3; ++d)
-            part[3 * blockIdx.x + d] = sh[d][0];
+        for (int k = 0; k < 3; ++k)
+            part[(blockIdx.y * kRedBlocks + blockIdx.x) * 3 + k] = sh[k][0];
 }
 
 __global__ void k_momentum_final(const double *__restrict__ part, double *__restrict__ out)
@@ -396,51 +566,53 @@ __global__ void k_momentum_final(const double *__restrict__ part, double *__rest
     if (threadIdx.x < 3) {
         double s = 0.0;
         for (int b = 0; b < kRedBlocks; ++b)
-            s += part[3 * b + threadIdx.x];
-        out[threadIdx.x] = s;
+            s += part[(blockIdx.x * kRedBlocks + b) * 3 + threadIdx.x];
+        out[3 * blockIdx.x + threadIdx.x] = s;
     }
 }
 
-struct ForceScratch {
-    BinScratch bin;
-    int *offsets;
-    int *perm;
-    float4 *sorted;
-    int *chunk_count;
-    int *item_off;    // [ncell + 1]; item_off[ncell] = number of items
-    int *scan_part2;
-    int4 *items;
-    double *mom_part;
-};
-
-int64_t item_bound(int64_t n, int ncell)
+unsigned grid_for_items(int64_t ub)
 {
-    int64_t nonempty = n < ncell ? n : ncell;
-    return nonempty + n / 16 + 1;  // see chunks_for
+    return (unsigned)((ub + 511) & ~int64_t(511));
 }
 
-void force_layout(Bump &b, int64_t n, const Geom &g, ForceScratch &s)
+int lpt_blocks(int64_t ub)
 {
-    size_t nn = (size_t)(n > 0 ? n : 1);
-    bin_layout(b, n, g, s.bin);
-    s.offsets = b.take<int>((size_t)g.ncell + 1);
+    return (int)((ub + kLptBlock - 1) / kLptBlock);
+}
+
+}  // namespace
+
+int64_t item_bound(int64_t ntot, int64_t ctot)
+{
+    int64_t nonempty = ntot < ctot ? ntot : ctot;
+    return nonempty + ntot / 16 + 1;  // see chunks_for
+}
+
+void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s)
+{
+    size_t nn = (size_t)(ntot > 0 ? ntot : 1);
+    const int64_t ub = item_bound(ntot, ctot);
+    bin_layout(b, ntot, ctot, nb, s.bin);
+    s.offsets = b.take<int>((size_t)ctot + 1);
     s.perm = b.take<int>(nn);
     s.sorted = b.take<float4>(nn);
-    s.chunk_count = b.take<int>((size_t)g.ncell);
-    s.item_off = b.take<int>((size_t)g.ncell + 1);
-    scan_layout(b, g.ncell, &s.scan_part2);
-    s.items = b.take<int4>((size_t)item_bound(n, g.ncell));
-    s.mom_part = b.take<double>(3 * kRedBlocks);
+    s.chunk_count = b.take<int>((size_t)ctot);
+    s.item_off = b.take<int>((size_t)ctot + 1);
+    scan_layout(b, (int)ctot, &s.scan_part2);
+    s.items = b.take<int4>((size_t)ub);
+    s.item_cost = b.take<int>((size_t)ub);
+    s.items_lpt = b.take<int4>((size_t)ub);
+    const int nblk = lpt_blocks(ub);
+    s.lpt_hist = b.take<int>((size_t)32 * nblk);
+    s.lpt_off = b.take<int>((size_t)32 * nblk + 1);
+    scan_layout(b, 32 * nblk, &s.lpt_part);
+    s.queue = b.take<int>(1);
+    s.mom_part = b.take<double>((size_t)(nb > 0 ? nb : 1) * kRedBlocks * 3);
 }
 
-int check_force_args(sr_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
-                     const sr_box *box, double cell, float r_max, float eps, const float *poly,
-                     Geom *g)
+int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly)
 {
-    if (n < 0 || n > INT_MAX)
-        return sr_fail(ctx, SR_EINVAL, "n=%lld out of range", (long long)n);
-    if (n > 0 && (!x || !y || !z))
-        return sr_fail(ctx, SR_EINVAL, "NULL coordinate pointer");
     if (!poly)
         return sr_fail(ctx, SR_EINVAL, "poly is NULL");
     for (int k = 0; k < 6; ++k)
@@ -449,7 +621,14 @@ int check_force_args(sr_ctx *ctx, const float *x, const float *y, const float *z
     if (!(r_max > 0.f) || !std::isfinite(r_max))
         return sr_fail(ctx, SR_EINVAL, "r_max must be > 0");
     if (!(eps >= 1e-20f) || !std::isfinite(eps))
-        return sr_fail(ctx, SR_EINVAL, "eps must be >= 1e-20 (a pair at zero distance must stay finite)");
+        return sr_fail(ctx, SR_EINVAL,
+                       "eps must be >= 1e-20 (a pair at zero distance must stay finite)");
+    return SR_OK;
+}
+
+// Validates one box against the cutoff and returns the pair loop's geometry.
+int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int xsplit, Geom *g)
+{
     int rc = sr_make_geom(ctx, box, cell, g);
     if (rc)
         return rc;
@@ -457,16 +636,17 @@ int check_force_args(sr_ctx *ctx, const float *x, const float *y, const float *z
         double cs = g->len[d] / g->nc[d];  // chaining cell width
         if ((double)r_max > cs)
             return sr_fail(ctx, SR_EINVAL,
-                           "r_max=%g exceeds the cell width %g on axis %d: 27 cells would not cover the cutoff",
+                           "r_max=%g exceeds the cell width %g on axis %d: 27 cells would not "
+                           "cover the cutoff",
                            (double)r_max, cs, d);
         if (g->periodic && g->nc[d] < 3)
-            return sr_fail(ctx, SR_EINVAL, "periodic box needs >= 3 cells per axis (axis %d has %d)",
-                           d, g->nc[d]);
+            return sr_fail(ctx, SR_EINVAL,
+                           "periodic box needs >= 3 cells per axis (axis %d has %d)", d,
+                           g->nc[d]);
         if (g->periodic && !(2.0 * (double)r_max < g->len[d]))
             return sr_fail(ctx, SR_EINVAL, "periodic box needs 2 r_max < L");
     }
-    // the pair loop's own (x-split) mesh
-    return sr_make_geom(ctx, box, cell, g, ctx ? ctx->xsplit : kMaxXsplit);
+    return sr_make_geom(ctx, box, cell, g, xsplit);
 }
 
 ForceParams make_params(float r_max, float eps, const float *poly)
@@ -493,34 +673,141 @@ ForceParams make_params(float r_max, float eps, const float *poly)
     return fp;
 }
 
-// Bin, gather and build work items (everything before the pair loop).
-int prepare(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *m, int n,
-            const Geom &g, ForceScratch &s)
+static int items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, int order)
 {
-    Bump sz{nullptr, 0, 0};
-    force_layout(sz, n, g, s);
-    int rc = sr_arena_reserve(ctx, sz.off);
+    int rc;
+    if ((rc = scan_enqueue(ctx, s.chunk_count, B.ctot, s.scan_part2, s.item_off)))
+        return rc;
+    hipLaunchKernelGGL(k_items, dim3((B.ctot + 255) / 256), dim3(256), 0, ctx->stream, B,
+                       s.offsets, s.item_off, s.items, s.item_cost);
+    if ((rc = sr_check_launch(ctx, "k_items")))
+        return rc;
+    if (order == 1) {
+        const int nblk = lpt_blocks(item_bound(B.ntot, B.ctot));
+        const int *n_items = s.item_off + B.ctot;
+        hipLaunchKernelGGL(k_lpt_hist, dim3(nblk), dim3(256), 0, ctx->stream, s.item_cost,
+                           n_items, nblk, s.lpt_hist);
+        if ((rc = scan_enqueue(ctx, s.lpt_hist, 32 * nblk, s.lpt_part, s.lpt_off)))
+            return rc;
+        hipLaunchKernelGGL(k_lpt_scatter, dim3(nblk), dim3(256), 0, ctx->stream, s.items,
+                           s.item_cost, n_items, nblk, s.lpt_off, s.items_lpt);
+        if ((rc = sr_check_launch(ctx, "k_lpt")))
+            return rc;
+    }
+    return SR_OK;
+}
+
+int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const ForceParams &fp,
+                  int order, int persistent, double *mom, int rec)
+{
+    int rc;
+    sr_timing_mark(ctx, rec, 0);
+    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count)))
+        return rc;
+    if ((rc = items_enqueue(ctx, B, s, order)))
+        return rc;
+    sr_timing_mark(ctx, rec, 1);
+    const int4 *items = order == 1 ? s.items_lpt : s.items;
+    const int *n_items = s.item_off + B.ctot;
+    if (B.ntot > 0) {
+        if (persistent) {
+            int dev_cus = 256;
+            (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount,
+                                        ctx->device);
+            const int64_t ub = item_bound(B.ntot, B.ctot);
+            int64_t grid = (int64_t)dev_cus * 24;
+            if (grid > ub)
+                grid = ub;
+            if ((rc = fill_enqueue(ctx, s.queue, 0, 1)))
+                return rc;
+            hipLaunchKernelGGL(k_force_persistent, dim3((unsigned)grid), dim3(64), 0, ctx->stream,
+                               B, items, n_items, s.sorted, s.offsets, s.perm, s.bin.mass_mixed,
+                               fp, s.queue);
+        } else {
+            hipLaunchKernelGGL(k_force, dim3(grid_for_items(item_bound(B.ntot, B.ctot))),
+                               dim3(64), 0, ctx->stream, B, items, n_items, s.sorted, s.offsets,
+                               s.perm, s.bin.mass_mixed, fp);
+        }
+        if ((rc = sr_check_launch(ctx, "k_force")))
+            return rc;
+    }
+    sr_timing_mark(ctx, rec, 2);
+    if (mom) {
+        hipLaunchKernelGGL(k_momentum_partial, dim3(kRedBlocks, B.nb), dim3(256), 0, ctx->stream,
+                           B, s.mom_part);
+        hipLaunchKernelGGL(k_momentum_final, dim3(B.nb), dim3(64), 0, ctx->stream, s.mom_part,
+                           mom);
+        if ((rc = sr_check_launch(ctx, "k_momentum")))
+            return rc;
+    }
+    return SR_OK;
+}
+
+// Batch of one box, by value.
+static int single_batch(sr_ctx *ctx, const float *x, const float *y, const float *z,
+                        const float *mass, int64_t n, const sr_box *box, double cell, float r_max,
+                        int xsplit, float *ax, float *ay, float *az, Batch *B)
+{
+    if (n < 0 || n > INT_MAX)
+        return sr_fail(ctx, SR_EINVAL, "n=%lld out of range", (long long)n);
+    if (n > 0 && (!x || !y || !z))
+        return sr_fail(ctx, SR_EINVAL, "NULL coordinate pointer");
+    *B = Batch{};
+    int rc = check_box_args(ctx, box, cell, r_max, xsplit, &B->one.g);
     if (rc)
         return rc;
-    Bump b{ctx->arena, 0, ctx->arena_cap};
-    force_layout(b, n, g, s);
-    if ((rc = bin_enqueue(ctx, x, y, z, m, n, g, s.bin, s.offsets, s.perm, s.sorted,
-                          s.chunk_count)))
-        return rc;
-    if ((rc = scan_enqueue(ctx, s.chunk_count, g.ncell, s.scan_part2, s.item_off)))
-        return rc;
-    hipLaunchKernelGGL(k_items, dim3((g.ncell + 255) / 256), dim3(256), 0, ctx->stream, s.offsets,
-                       s.item_off, g.ncell, s.items);
-    return sr_check_launch(ctx, "k_items");
+    B->nb = 1;
+    B->ntot = (int)n;
+    B->ctot = B->one.g.ncell;
+    B->one.n = (int)n;
+    B->one.x = x;
+    B->one.y = y;
+    B->one.z = z;
+    B->one.m = mass;
+    B->one.ax = ax;
+    B->one.ay = ay;
+    B->one.az = az;
+    return SR_OK;
 }
 
-unsigned item_grid(int64_t n, int ncell)
+extern "C" int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
+                              const float *oz, const float *mass, int64_t n, const sr_box *box,
+                              double cell, float r_max, float eps, const float poly[6], float *ax,
+                              float *ay, float *az, double *momentum3)
 {
-    int64_t ub = item_bound(n, ncell);
-    return (unsigned)((ub + 7) & ~int64_t(7));
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    int rc = check_force_params(ctx, r_max, eps, poly);
+    if (rc)
+        return rc;
+    if (!box || !box->periodic)
+        return sr_fail(ctx, SR_EINVAL, "split coordinates need a periodic box");
+    const int xs = ctx->xsplit < 3 ? ctx->xsplit : 3;
+    Batch B;
+    if ((rc = single_batch(ctx, ox, oy, oz, mass, n, box, cell, r_max, xs, ax, ay, az, &B)))
+        return rc;
+    if (n > 0 && (!cell3 || !mass || !ax || !ay || !az))
+        return sr_fail(ctx, SR_EINVAL, "NULL pointer");
+    for (int d = 0; d < 3; ++d)
+        if (B.one.g.nc[d] / (d == 0 ? xs : 1) > kSplitMaxCells)
+            return sr_fail(ctx, SR_EINVAL, "split coordinates allow at most %d cells per axis",
+                           kSplitMaxCells);
+    B.one.g.split = 1;
+    B.one.cell3 = cell3;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    Bump sz{nullptr, 0, 0};
+    ForceScratch s;
+    force_layout(sz, n, B.ctot, 1, s);
+    if ((rc = sr_arena_reserve(ctx, sz.off)))
+        return rc;
+    Bump b{ctx->arena, 0, ctx->arena_cap};
+    force_layout(b, n, B.ctot, 1, s);
+    const ForceParams fp = make_params(r_max, eps, poly);
+    const int rec = sr_timing_begin(ctx);
+    return force_enqueue(ctx, B, s, fp, ctx->order, ctx->persistent, momentum3, rec);
 }
-
-}  // namespace
 
 extern "C" int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force,
                                 size_t *bytes)
@@ -534,10 +821,10 @@ extern "C" int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int w
     Bump sz{nullptr, 0, 0};
     if (with_force) {
         ForceScratch s;
-        force_layout(sz, n, g, s);
+        force_layout(sz, n, g.ncell, 1, s);
     } else {
         BinScratch s;
-        bin_layout(sz, n, g, s);
+        bin_layout(sz, n, g.ncell, 1, s);
     }
     *bytes = sz.off;
     return SR_OK;
@@ -551,38 +838,26 @@ extern "C" int sr_force(sr_ctx *ctx, const float *x, const float *y, const float
     if (!ctx)
         return SR_EINVAL;
     ctx->err.clear();
-    Geom g;
-    int rc = check_force_args(ctx, x, y, z, n, box, cell, r_max, eps, poly, &g);
+    int rc = check_force_params(ctx, r_max, eps, poly);
     if (rc)
+        return rc;
+    Batch B;
+    if ((rc = single_batch(ctx, x, y, z, mass, n, box, cell, r_max, ctx->xsplit, ax, ay, az, &B)))
         return rc;
     if (n > 0 && (!mass || !ax || !ay || !az))
         return sr_fail(ctx, SR_EINVAL, "NULL mass or output pointer");
     if (hipSetDevice(ctx->device) != hipSuccess)
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    Bump sz{nullptr, 0, 0};
     ForceScratch s;
-    const int rec = sr_timing_begin(ctx);
-    sr_timing_mark(ctx, rec, 0);
-    if ((rc = prepare(ctx, x, y, z, mass, (int)n, g, s)))
+    force_layout(sz, n, B.ctot, 1, s);
+    if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
+    Bump b{ctx->arena, 0, ctx->arena_cap};
+    force_layout(b, n, B.ctot, 1, s);
     const ForceParams fp = make_params(r_max, eps, poly);
-    sr_timing_mark(ctx, rec, 1);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_force, dim3(item_grid(n, g.ncell)), dim3(64), 0, ctx->stream,
-                           s.items, s.item_off + g.ncell, s.sorted, s.offsets, s.perm,
-                           s.bin.mass_mixed, g, fp, ax, ay, az);
-        if ((rc = sr_check_launch(ctx, "k_force")))
-            return rc;
-    }
-    sr_timing_mark(ctx, rec, 2);
-    if (momentum3) {
-        hipLaunchKernelGGL(k_momentum_partial, dim3(kRedBlocks), dim3(256), 0, ctx->stream, mass,
-                           ax, ay, az, (int)n, s.mom_part);
-        hipLaunchKernelGGL(k_momentum_final, dim3(1), dim3(64), 0, ctx->stream, s.mom_part,
-                           momentum3);
-        if ((rc = sr_check_launch(ctx, "k_momentum")))
-            return rc;
-    }
-    return SR_OK;
+    const int rec = sr_timing_begin(ctx);
+    return force_enqueue(ctx, B, s, fp, ctx->order, ctx->persistent, momentum3, rec);
 }
 
 extern "C" int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const float *z,
@@ -595,25 +870,34 @@ extern "C" int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const 
     if (!useful || !candidates)
         return sr_fail(ctx, SR_EINVAL, "NULL result pointer");
     static const float zero_poly[6] = {0, 0, 0, 0, 0, 0};
-    Geom g;
-    int rc = check_force_args(ctx, x, y, z, n, box, cell, r_max, 1.0f, zero_poly, &g);
+    Batch B;
+    // masses are not needed; the gather reads x in their place
+    int rc = single_batch(ctx, x, y, z, x, n, box, cell, r_max, ctx->xsplit, nullptr, nullptr,
+                          nullptr, &B);
     if (rc)
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
-    // masses are not needed; the gather reads x as a stand-in (w is unused)
+    Bump sz{nullptr, 0, 0};
     ForceScratch s;
-    if ((rc = prepare(ctx, x, y, z, x, (int)n, g, s)))
+    force_layout(sz, n, B.ctot, 1, s);
+    if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
-    // eps = 0 so that se = s and the test is s < r_max^2 exactly as in sr_force
+    Bump b{ctx->arena, 0, ctx->arena_cap};
+    force_layout(b, n, B.ctot, 1, s);
+    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count)))
+        return rc;
+    if ((rc = items_enqueue(ctx, B, s, 0)))
+        return rc;
+    // eps = 0 so that se = s and the test is s < r_max^2
     ForceParams fp = make_params(r_max, 0.0f, zero_poly);
     unsigned long long *st = (unsigned long long *)ctx->stats;
     if ((rc = fill_enqueue(ctx, (int *)st, 0, 4)))
         return rc;
     if (n > 0) {
-        hipLaunchKernelGGL(k_pair_stats, dim3((unsigned)item_bound(n, g.ncell)), dim3(64), 0,
-                           ctx->stream, s.items, s.item_off + g.ncell, s.sorted, s.offsets,
-                           s.perm, g, fp, per_target, st);
+        hipLaunchKernelGGL(k_pair_stats, dim3((unsigned)item_bound(n, B.ctot)), dim3(64), 0,
+                           ctx->stream, B, s.items, s.item_off + B.ctot, s.sorted, s.offsets,
+                           s.perm, fp, per_target, st);
         if ((rc = sr_check_launch(ctx, "k_pair_stats")))
             return rc;
     }

@@ -21,6 +21,8 @@ struct sr_ctx {
     int64_t *stats = nullptr;   // device counters for sr_pair_stats
     std::string err;
     int xsplit = 2;             // sub-cells per chaining cell along x in sr_force
+    int order = 1;              // work-item order: 0 cell order, 1 cost buckets (LPT)
+    int persistent = 0;         // 1: persistent workgroups pull items from a counter
     bool timing = false;        // record events around sr_force phases
     std::vector<hipEvent_t> events;  // 3 per recorded call
     size_t events_used = 0;
@@ -34,18 +36,72 @@ struct sr_ctx {
 // (2 hx + 1) x 3 x 3 cells.  Rows along x stay contiguous in the sorted
 // order, and the searched x extent shrinks from 3 to 2 + 1/hx chaining
 // cells (fewer candidate pairs for the same cutoff).
+//
+// Split coordinates (split != 0, periodic boxes only): a particle is given
+// as its chaining cell (cx, cy, cz), packed 10 bits each into cell3, and a
+// float32 offset from that cell's lower corner.  The pair loop then works
+// entirely in cell-relative float32 coordinates (w = cell widths, FP64).
 struct Geom {
     double len[3];
     double inv[3];
+    double w[3];
     float lenf[3];
     int nc[3];
     int ncell;
     int periodic;
     int hx;
+    int split;
     double skin;
 };
 
+constexpr int kSplitMaxCells = 1023;  // per axis, split coordinates
+
 constexpr int kMaxXsplit = 4;
+
+// One box of a batch.  Particles of all boxes are numbered consecutively
+// (box b owns [pbase, pbase + n)) and so are their cells ([cbase, cbase +
+// g.ncell)); inputs and outputs stay in the caller's per-box arrays.
+struct BoxDesc {
+    Geom g;
+    int pbase, n, cbase, _pad;
+    const float *x, *y, *z, *m;   // positions, or cell offsets when g.split
+    const int *cell3;             // split coordinates: packed chaining cells
+    float *ax, *ay, *az;
+};
+
+// A batch as the kernels see it (passed by value).  A single box travels
+// inside the kernel arguments (`one`); larger batches read a device table.
+struct Batch {
+    const BoxDesc *boxes;  // device table, or nullptr when nb == 1
+    const int *pstart;     // [nb + 1] first particle of each box
+    const int *cstart;     // [nb + 1] first cell of each box
+    int nb;
+    int ntot;
+    int ctot;
+    int _pad;
+    BoxDesc one;
+};
+
+// Largest b with start[b] <= v (boxes with no particles are skipped).
+__device__ __forceinline__ int find_box(const int *start, int nb, int v)
+{
+    if (nb == 1)
+        return 0;
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const BoxDesc &box_at(const Batch &B, int b)
+{
+    return B.boxes ? B.boxes[b] : B.one;
+}
 
 // Scalars of the pair loop in the form the kernel evaluates.
 //   se = s + eps is formed directly by the FMA chain, the cutoff test is
@@ -75,15 +131,40 @@ struct Bump {
 
 // Scratch of one binning pass (sorted-slot order), carved from the arena.
 struct BinScratch {
-    int *cid;         // [n] cell id of each original particle
-    int *slot;        // [n] arrival rank within its cell (atomic, unordered)
-    int *count;       // [ncell] particles per cell
+    int *cid;         // [ntot] global cell id of each particle
+    int *slot;        // [ntot] arrival rank within its cell (atomic, unordered)
+    int *count;       // [ctot] particles per cell
     int *scan_part;   // [scan tiles] partial sums
-    int *tmp;         // [n] ping-pong buffer of the large-cell merge
+    int *tmp;         // [ntot] ping-pong buffer of the large-cell merge
     int *large_list;  // [max_large] cells too big for one wavefront's LDS
     int *large_count; // [1]
-    int *mass_mixed;  // [1] set to 1 by the gather if any mass differs from m[0]
+    int *mass_mixed;  // [nb] box b: 1 if any of its masses differs from its first
 };
+
+// Everything a force pass needs beyond binning.
+struct ForceScratch {
+    BinScratch bin;
+    int *offsets;     // [ctot + 1]
+    int *perm;        // [ntot]
+    float4 *sorted;   // [ntot] (x, y, z, m) in cell order
+    int *chunk_count; // [ctot]
+    int *item_off;    // [ctot + 1]; item_off[ctot] = number of items
+    int *scan_part2;
+    int4 *items;      // [item bound] in cell order
+    int *item_cost;   // [item bound] cost bucket of each item
+    int4 *items_lpt;  // [item bound] items by decreasing cost bucket
+    int *lpt_hist;    // [32 * lpt blocks] key-major per-block counts
+    int *lpt_off;     // [32 * lpt blocks + 1] their exclusive scan
+    int *lpt_part;
+    int *queue;       // [1] persistent work counter
+    double *mom_part; // [nb * kRedBlocks * 3]
+};
+
+constexpr int kRedBlocks = 64;     // FP64 reduction blocks per box
+constexpr int kLargeCell = 1024;   // cells above this are sorted by a whole block
+constexpr int kChunk = 64;         // maximum targets per force work item
+constexpr int kMaxSplit = 16;      // at most 16 lane groups share one target
+constexpr int kLptBlock = 1024;    // items per block of the cost-bucket sort
 
 // Host helpers (sr_ctx.cpp)
 int sr_fail(sr_ctx *ctx, int code, const char *fmt, ...);
@@ -95,17 +176,25 @@ int sr_timing_begin(sr_ctx *ctx);
 void sr_timing_mark(sr_ctx *ctx, int rec, int which);
 
 // Binning (sr_bin.hip)
-void bin_layout(Bump &b, int64_t n, const Geom &g, BinScratch &s);
-int bin_enqueue(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *m,
-                int n, const Geom &g, const BinScratch &s, int *offsets, int *perm,
+void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s);
+int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, int *perm,
                 float4 *sorted, int *chunk_count);
 void scan_layout(Bump &b, int m, int **part);
 int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out);
 int fill_enqueue(sr_ctx *ctx, int *p, int value, int64_t count);
 
-constexpr int kLargeCell = 1024;   // cells above this are sorted by a whole block
-constexpr int kChunk = 64;         // maximum targets per force work item
-constexpr int kMaxSplit = 16;      // at most 16 lane groups share one target
+// Force pass (sr_force.hip)
+int64_t item_bound(int64_t ntot, int64_t ctot);
+void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s);
+int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int xsplit,
+                   Geom *g);
+int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly);
+ForceParams make_params(float r_max, float eps, const float *poly);
+// Enqueue bin + items (+ cost order) + pair loop + momentum for a batch.
+// order: 0 cell order, 1 cost buckets; persistent: one wave per CU slot
+// pulling items from a counter.  mom: device double[3 * nb] or nullptr.
+int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const ForceParams &fp,
+                  int order, int persistent, double *mom, int timing_rec);
 
 // A force work item with nt targets gives each target S = floor(64/nt)
 // lanes (capped), which take disjoint slices of every source tile.
@@ -115,17 +204,20 @@ __host__ __device__ inline int split_for(int nt)
     return s < 1 ? 1 : (s > kMaxSplit ? kMaxSplit : s);
 }
 
-// Number of work items a cell of n targets is cut into: the cheapest
-// candidate count under a cost model in which an item costs 1/S of a
-// full-wavefront pass over its sources plus 5 % fixed overhead.  Chunk k of
-// q covers targets [k n / q, (k + 1) n / q).
+// Number of work items a cell of n targets is cut into.  Up to 256 targets
+// the cheapest candidate count under a cost model in which an item costs
+// 1/S of a full-wavefront pass over its sources plus 5 % fixed overhead;
+// beyond, chunks of at most 64 (S = 1 is then efficient).  Chunk k of q
+// covers targets [k n / q, (k + 1) n / q).  The count never exceeds
+// max(ceil(n / 64), n / 16), which bounds the items by (non-empty cells) +
+// n / 16.
 __host__ __device__ inline int chunks_for(int n)
 {
     if (n <= 0)
         return 0;
     const int q0 = (n + kChunk - 1) / kChunk;
-    // chunks below 16 targets never pay off (S is capped); this also bounds
-    // the item count by (non-empty cells) + n / 16
+    if (n > 4 * kChunk)
+        return q0;
     const int qmax = q0 > n / 16 ? q0 : n / 16;
     float best = 3.0e38f;
     int bq = q0;

@@ -1,0 +1,35 @@
+// Split coordinates and the serving state update (sr_split.hip).
+#pragma once
+
+#include "sr_internal.h"
+
+// Chaining-mesh geometry of split coordinates: h = len / nc, FP64.
+struct SplitGeom {
+    double len[3];
+    double inv[3];
+    double h[3];
+    int nc[3];
+    int _pad;
+};
+
+// One serving slot: resident split state of one box (device pointers).
+
+struct SlotState {
+    SplitGeom g;
+    float dt;
+    int _pad;
+    int *cell3;
+    float *ox, *oy, *oz;
+    float *vx, *vy, *vz;
+    const float *ax, *ay, *az;
+};
+
+int split_geom(sr_ctx *ctx, const sr_box *box, double cell, SplitGeom *sg);
+int split_from_f64_enqueue(sr_ctx *ctx, const double *x, const double *y, const double *z, int n,
+                           const SplitGeom &sg, int *cell3, float *ox, float *oy, float *oz);
+int split_to_f64_enqueue(sr_ctx *ctx, const int *cell3, const float *ox, const float *oy,
+                         const float *oz, int n, const SplitGeom &sg, double *x, double *y,
+                         double *z);
+// mode 0: stream half step; mode 1: kick then stream half step.
+int slot_update_enqueue(sr_ctx *ctx, const SlotState *slots, const int *start, int nslot,
+                        int ntot, int mode);

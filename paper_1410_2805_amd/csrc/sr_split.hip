@@ -1,0 +1,239 @@
+// Split (cell + float32 offset) coordinates: conversion from and to float64
+// positions, and the stream / kick maps of the stream-kick-stream step
+// (Sec. 2.5) applied to resident split state.
+//
+// A coordinate of a periodic box of side L meshed into n_c chaining cells of
+// width h = L / n_c is held as c = floor(x / h) (packed 10 bits per axis into
+// cell3) and o = fl32(x - c h) in [0, h).  Offsets carry ulp(h) rounding
+// instead of ulp(L), and the pair loop differences them without forming
+// global coordinates (sr_force.hip).
+#include <climits>
+#include <cmath>
+
+#include "sr_internal.h"
+#include "sr_split.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int pack3(const int c[3])
+{
+    return c[0] | (c[1] << 10) | (c[2] << 20);
+}
+
+__device__ __forceinline__ void unpack3(int p, int c[3])
+{
+    c[0] = p & 1023;
+    c[1] = (p >> 10) & 1023;
+    c[2] = (p >> 20) & 1023;
+}
+
+// Re-home an offset that left [0, h): at most a few cells per call (the
+// caller keeps |v dt| well below h); wraps the cell index periodically.
+__device__ __forceinline__ void rehome(double &o, int &c, double h, int nc)
+{
+    while (o >= h) {
+        o -= h;
+        c = c + 1 == nc ? 0 : c + 1;
+    }
+    while (o < 0.0) {
+        o += h;
+        c = c == 0 ? nc - 1 : c - 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_from_f64(const double *__restrict__ x,
+                                                     const double *__restrict__ y,
+                                                     const double *__restrict__ z, int n,
+                                                     SplitGeom sg, int *__restrict__ cell3,
+                                                     float *__restrict__ ox,
+                                                     float *__restrict__ oy,
+                                                     float *__restrict__ oz,
+                                                     int *__restrict__ status)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const double p[3] = {x[i], y[i], z[i]};
+    int c[3];
+    float o[3];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (!(p[k] >= 0.0 && p[k] < sg.len[k])) {
+            bad = true;
+            c[k] = 0;
+            o[k] = 0.f;
+            continue;
+        }
+        int ci = (int)floor(p[k] * sg.inv[k]);
+        ci = ci < sg.nc[k] - 1 ? ci : sg.nc[k] - 1;
+        double off = p[k] - (double)ci * sg.h[k];
+        rehome(off, ci, sg.h[k], sg.nc[k]);
+        c[k] = ci;
+        o[k] = (float)off;
+    }
+    if (bad)
+        atomicOr(status, 1);
+    cell3[i] = pack3(c);
+    ox[i] = o[0];
+    oy[i] = o[1];
+    oz[i] = o[2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f64(const int *__restrict__ cell3,
+                                                   const float *__restrict__ ox,
+                                                   const float *__restrict__ oy,
+                                                   const float *__restrict__ oz, int n,
+                                                   SplitGeom sg, double *__restrict__ x,
+                                                   double *__restrict__ y,
+                                                   double *__restrict__ z)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    int c[3];
+    unpack3(cell3[i], c);
+    const float o[3] = {ox[i], oy[i], oz[i]};
+    double *out[3] = {x, y, z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double v = (double)c[k] * sg.h[k] + (double)o[k];
+        if (v >= sg.len[k])
+            v -= sg.len[k];
+        out[k][i] = v;
+    }
+}
+
+// Serving state update over all slots of a tick (slot s owns particles
+// [start[s], start[s+1]) of the concatenated numbering).
+//   mode 0: stream  o += v dt/2 (re-home);
+//   mode 1: kick v += a dt, then stream o += v dt/2 (re-home).
+__global__ __launch_bounds__(kBlock) void k_slot_update(const SlotState *__restrict__ slots,
+                                                        const int *__restrict__ start, int nslot,
+                                                        int ntot, int mode)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= ntot)
+        return;
+    int lo = 0, hi = nslot - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SlotState &S = slots[lo];
+    const int li = i - start[lo];
+    float v[3] = {S.vx[li], S.vy[li], S.vz[li]};
+    if (mode == 1) {
+        v[0] = fmaf(S.ax[li], S.dt, v[0]);
+        v[1] = fmaf(S.ay[li], S.dt, v[1]);
+        v[2] = fmaf(S.az[li], S.dt, v[2]);
+        S.vx[li] = v[0];
+        S.vy[li] = v[1];
+        S.vz[li] = v[2];
+    }
+    int c[3];
+    unpack3(S.cell3[li], c);
+    float *o[3] = {S.ox, S.oy, S.oz};
+    const double half = 0.5 * (double)S.dt;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double off = (double)o[k][li] + (double)v[k] * half;
+        rehome(off, c[k], S.g.h[k], S.g.nc[k]);
+        o[k][li] = (float)off;
+    }
+    S.cell3[li] = pack3(c);
+}
+
+}  // namespace
+
+int split_geom(sr_ctx *ctx, const sr_box *box, double cell, SplitGeom *sg)
+{
+    Geom g;
+    int rc = sr_make_geom(ctx, box, cell, &g);
+    if (rc)
+        return rc;
+    if (!box->periodic)
+        return sr_fail(ctx, SR_EINVAL, "split coordinates need a periodic box");
+    for (int d = 0; d < 3; ++d) {
+        if (g.nc[d] > kSplitMaxCells)
+            return sr_fail(ctx, SR_EINVAL, "split coordinates allow at most %d cells per axis",
+                           kSplitMaxCells);
+        sg->len[d] = g.len[d];
+        sg->inv[d] = g.inv[d];
+        sg->h[d] = g.w[d];
+        sg->nc[d] = g.nc[d];
+    }
+    return SR_OK;
+}
+
+int split_from_f64_enqueue(sr_ctx *ctx, const double *x, const double *y, const double *z, int n,
+                           const SplitGeom &sg, int *cell3, float *ox, float *oy, float *oz)
+{
+    if (n <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_from_f64, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, ctx->stream,
+                       x, y, z, n, sg, cell3, ox, oy, oz, ctx->status);
+    return sr_check_launch(ctx, "k_from_f64");
+}
+
+int split_to_f64_enqueue(sr_ctx *ctx, const int *cell3, const float *ox, const float *oy,
+                         const float *oz, int n, const SplitGeom &sg, double *x, double *y,
+                         double *z)
+{
+    if (n <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_to_f64, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, ctx->stream,
+                       cell3, ox, oy, oz, n, sg, x, y, z);
+    return sr_check_launch(ctx, "k_to_f64");
+}
+
+int slot_update_enqueue(sr_ctx *ctx, const SlotState *slots, const int *start, int nslot,
+                        int ntot, int mode)
+{
+    if (ntot <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_slot_update, dim3((ntot + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       ctx->stream, slots, start, nslot, ntot, mode);
+    return sr_check_launch(ctx, "k_slot_update");
+}
+
+extern "C" int sr_split_from_f64(sr_ctx *ctx, const double *x, const double *y, const double *z,
+                                 int64_t n, const sr_box *box, double cell, int32_t *cell3,
+                                 float *ox, float *oy, float *oz)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > INT_MAX || (n > 0 && (!x || !y || !z || !cell3 || !ox || !oy || !oz)))
+        return sr_fail(ctx, SR_EINVAL, "bad size or NULL pointer");
+    SplitGeom sg;
+    int rc = split_geom(ctx, box, cell, &sg);
+    if (rc)
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    return split_from_f64_enqueue(ctx, x, y, z, (int)n, sg, cell3, ox, oy, oz);
+}
+
+extern "C" int sr_split_to_f64(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
+                               const float *oz, int64_t n, const sr_box *box, double cell,
+                               double *x, double *y, double *z)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > INT_MAX || (n > 0 && (!x || !y || !z || !cell3 || !ox || !oy || !oz)))
+        return sr_fail(ctx, SR_EINVAL, "bad size or NULL pointer");
+    SplitGeom sg;
+    int rc = split_geom(ctx, box, cell, &sg);
+    if (rc)
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    return split_to_f64_enqueue(ctx, cell3, ox, oy, oz, (int)n, sg, x, y, z);
+}

@@ -30,7 +30,8 @@ class SRError(RuntimeError):
 class Tuning(ctypes.Structure):
     """sr_tuning: pair-loop tiling knobs."""
 
-    _fields_ = [("xsplit", ctypes.c_int32), ("_reserved", ctypes.c_int32 * 3)]
+    _fields_ = [("xsplit", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("cell_scale", ctypes.c_float)]
 
 
 class Box(ctypes.Structure):
@@ -49,6 +50,41 @@ class Box(ctypes.Structure):
         b.periodic = 1 if periodic else 0
         b.skin = float(skin)
         return b
+
+
+class BatchBox(ctypes.Structure):
+    """sr_batch_box: one box of a plan (device pointers)."""
+
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("mass", ctypes.c_void_p), ("n", ctypes.c_int64), ("box", Box),
+                ("cell", ctypes.c_double), ("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p),
+                ("az", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("len", ctypes.c_double), ("steps", ctypes.c_int32),
+                ("dt", ctypes.c_float),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p), ("vz", ctypes.c_void_p),
+                ("mass", ctypes.c_void_p),
+                ("out_x", ctypes.c_void_p), ("out_y", ctypes.c_void_p), ("out_z", ctypes.c_void_p),
+                ("out_vx", ctypes.c_void_p), ("out_vy", ctypes.c_void_p),
+                ("out_vz", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("r_max", ctypes.c_float), ("eps", ctypes.c_float), ("poly", ctypes.c_float * 6),
+                ("cell", ctypes.c_double), ("tuning", Tuning)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("draining", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("state_bytes_in_use", ctypes.c_size_t),
+                ("state_bytes_high_water", ctypes.c_size_t),
+                ("state_bytes_capacity", ctypes.c_size_t),
+                ("scratch_bytes_capacity", ctypes.c_size_t), ("ticks", ctypes.c_int64)]
 
 
 def _load():
@@ -73,6 +109,28 @@ def _load():
                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "sr_timing_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "sr_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
+        "sr_split_from_f64": (ctypes.c_int, [P, P, P, P, i64, BP, f64, P, P, P, P]),
+        "sr_split_to_f64": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, P, P, P]),
+        "sr_force_split": (ctypes.c_int, [P, P, P, P, P, P, i64, BP, f64, f32, f32, P, P, P, P,
+                                          P]),
+        "sr_plan_create": (ctypes.c_int, [P, ctypes.POINTER(BatchBox), ctypes.c_int, f32, f32, P,
+                                          P, ctypes.POINTER(P)]),
+        "sr_plan_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
+        "sr_plan_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
+        "sr_plan_run": (ctypes.c_int, [P]),
+        "sr_plan_capture": (ctypes.c_int, [P]),
+        "sr_plan_launch": (ctypes.c_int, [P]),
+        "sr_plan_autotune": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(Tuning),
+                                            ctypes.POINTER(f64)]),
+        "sr_plan_destroy": (ctypes.c_int, [P]),
+        "sr_server_create": (ctypes.c_int, [P, ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]),
+        "sr_server_submit": (ctypes.c_int, [P, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
+        "sr_server_tick": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int)]),
+        "sr_server_poll": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]),
+        "sr_server_cancel": (ctypes.c_int, [P, i64]),
+        "sr_server_info_get": (ctypes.c_int, [P, ctypes.POINTER(ServerInfo)]),
+        "sr_server_destroy": (ctypes.c_int, [P]),
         "sr_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "sr_timing_collect": (ctypes.c_int, [P, ctypes.POINTER(f64), ctypes.POINTER(f64),
                                              ctypes.POINTER(i64)]),
@@ -90,7 +148,12 @@ lib = _load()
 def exported_symbols() -> list[str]:
     return ["sr_ctx_create", "sr_ctx_destroy", "sr_last_error", "sr_set_stream", "sr_arena_info",
             "sr_sync", "sr_grid_dims", "sr_scratch_bytes", "sr_bin", "sr_force", "sr_pair_stats",
-            "sr_timing_enable", "sr_timing_collect", "sr_set_tuning", "sr_get_tuning"]
+            "sr_timing_enable", "sr_timing_collect", "sr_set_tuning", "sr_get_tuning",
+            "sr_split_from_f64", "sr_split_to_f64", "sr_force_split",
+            "sr_plan_create", "sr_plan_set_tuning", "sr_plan_get_tuning", "sr_plan_run",
+            "sr_plan_capture", "sr_plan_launch", "sr_plan_autotune", "sr_plan_destroy",
+            "sr_server_create", "sr_server_submit", "sr_server_tick", "sr_server_poll",
+            "sr_server_cancel", "sr_server_info_get", "sr_server_destroy"]
 
 
 def _ptr(t):
@@ -164,15 +227,20 @@ class Context:
     def sync(self):
         self._check(lib.sr_sync(self._h))
 
-    def set_tuning(self, xsplit: int):
+    def set_tuning(self, xsplit: int | None = None, order: int | None = None,
+                   persistent: int | None = None):
+        cur = self.get_tuning()
         t = Tuning()
-        t.xsplit = int(xsplit)
+        t.xsplit = int(cur["xsplit"] if xsplit is None else xsplit)
+        t.order = int(cur["order"] if order is None else order)
+        t.persistent = int(cur["persistent"] if persistent is None else persistent)
+        t.cell_scale = 1.0
         self._check(lib.sr_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
         self._check(lib.sr_get_tuning(self._h, ctypes.byref(t)))
-        return {"xsplit": int(t.xsplit)}
+        return {"xsplit": int(t.xsplit), "order": int(t.order), "persistent": int(t.persistent)}
 
     def timing_enable(self, on: bool = True):
         self._check(lib.sr_timing_enable(self._h, int(bool(on))))
@@ -228,6 +296,59 @@ def sr_force(ctx: Context, x, y, z, m, box: Box, cell: float, r_max: float, eps:
     return ax, ay, az, mom
 
 
+def _typed(t, n, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and t.dim() == 1 and t.shape[0] == n):
+        raise ValueError("%s must be a contiguous 1-D %s CUDA tensor of length %d" % (name, dtype, n))
+    return _ptr(t)
+
+
+def sr_split_from_f64(ctx: Context, x, y, z, box: Box, cell: float):
+    """float64 positions -> (cell3 int32, ox, oy, oz float32) on the device."""
+    n = int(x.shape[0])
+    dev = x.device
+    cell3 = torch.empty(max(n, 1), dtype=torch.int32, device=dev)[:n]
+    o = tuple(torch.empty(max(n, 1), dtype=torch.float32, device=dev)[:n] for _ in range(3))
+    ctx._bind_stream()
+    ctx._check(lib.sr_split_from_f64(ctx._h, _typed(x, n, torch.float64, "x"),
+                                     _typed(y, n, torch.float64, "y"),
+                                     _typed(z, n, torch.float64, "z"), n, ctypes.byref(box),
+                                     float(cell), _ptr(cell3), _ptr(o[0]), _ptr(o[1]),
+                                     _ptr(o[2])))
+    return cell3, o[0], o[1], o[2]
+
+
+def sr_split_to_f64(ctx: Context, cell3, ox, oy, oz, box: Box, cell: float):
+    n = int(cell3.shape[0])
+    dev = cell3.device
+    out = tuple(torch.empty(max(n, 1), dtype=torch.float64, device=dev)[:n] for _ in range(3))
+    ctx._bind_stream()
+    ctx._check(lib.sr_split_to_f64(ctx._h, _typed(cell3, n, torch.int32, "cell3"),
+                                   _f32(ox, n, "ox"), _f32(oy, n, "oy"), _f32(oz, n, "oz"), n,
+                                   ctypes.byref(box), float(cell), _ptr(out[0]), _ptr(out[1]),
+                                   _ptr(out[2])))
+    return out
+
+
+def sr_force_split(ctx: Context, cell3, ox, oy, oz, m, box: Box, cell: float, r_max: float,
+                   eps: float, poly, out=None, momentum: bool = False):
+    """sr_force on split coordinates; returns (ax, ay, az, momentum3 or None)."""
+    n = int(cell3.shape[0])
+    dev = cell3.device
+    if out is None:
+        out = tuple(torch.empty(max(n, 1), dtype=torch.float32, device=dev)[:n] for _ in range(3))
+    ax, ay, az = out
+    mom = torch.zeros(3, dtype=torch.float64, device=dev) if momentum else None
+    c = (ctypes.c_float * 6)(*[float(v) for v in poly])
+    ctx._bind_stream()
+    ctx._check(lib.sr_force_split(ctx._h, _typed(cell3, n, torch.int32, "cell3"),
+                                  _f32(ox, n, "ox"), _f32(oy, n, "oy"), _f32(oz, n, "oz"),
+                                  _f32(m, n, "mass"), n, ctypes.byref(box), float(cell),
+                                  float(r_max), float(eps), c, _f32(ax, n, "ax"),
+                                  _f32(ay, n, "ay"), _f32(az, n, "az"), _ptr(mom)))
+    return ax, ay, az, mom
+
+
 def sr_pair_stats(ctx: Context, x, y, z, box: Box, cell: float, r_max: float,
                   per_target: bool = False):
     """Returns (useful, candidates, per_target int32[n] or None); waits."""
@@ -239,3 +360,181 @@ def sr_pair_stats(ctx: Context, x, y, z, box: Box, cell: float, r_max: float,
                                  ctypes.byref(box), float(cell), float(r_max), _ptr(pt),
                                  ctypes.byref(u), ctypes.byref(c)))
     return int(u.value), int(c.value), pt
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    return {"xsplit": int(t.xsplit), "order": int(t.order), "persistent": int(t.persistent),
+            "cell_scale": float(t.cell_scale)}
+
+
+class Plan:
+    """sr_plan: a batch of independent boxes evaluated in one pass.
+
+    boxes: list of dicts with device tensors x, y, z, m, outputs ax, ay, az,
+    and box (Box), cell (float).  The tensors must outlive the plan."""
+
+    def __init__(self, ctx: Context, boxes, r_max: float, eps: float, poly, momentum=None):
+        self.ctx = ctx
+        arr = (BatchBox * len(boxes))()
+        self._keep = []
+        for i, b in enumerate(boxes):
+            n = int(b["x"].shape[0])
+            for k in ("x", "y", "z", "m", "ax", "ay", "az"):
+                _f32(b[k], n, k)
+                self._keep.append(b[k])
+            arr[i].x, arr[i].y, arr[i].z = (b[k].data_ptr() for k in "xyz")
+            arr[i].mass = b["m"].data_ptr()
+            arr[i].n = n
+            arr[i].box = b["box"]
+            arr[i].cell = float(b["cell"])
+            arr[i].ax, arr[i].ay, arr[i].az = (b[k].data_ptr() for k in ("ax", "ay", "az"))
+        if momentum is not None:
+            if not (momentum.is_cuda and momentum.dtype == torch.float64
+                    and momentum.numel() == 3 * len(boxes) and momentum.is_contiguous()):
+                raise ValueError("momentum must be a contiguous float64[3 * nboxes] CUDA tensor")
+            self._keep.append(momentum)
+        c = (ctypes.c_float * 6)(*[float(v) for v in poly])
+        h = ctypes.c_void_p()
+        ctx._bind_stream()
+        ctx._check(lib.sr_plan_create(ctx._h, arr, len(boxes), float(r_max), float(eps), c,
+                                      _ptr(momentum), ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        self.ctx._check(lib.sr_plan_run(self._h))
+
+    def capture(self):
+        self.ctx._check(lib.sr_plan_capture(self._h))
+
+    def launch(self):
+        self.ctx._check(lib.sr_plan_launch(self._h))
+
+    def set_tuning(self, xsplit: int, order: int, persistent: int, cell_scale: float = 1.0):
+        t = Tuning()
+        t.xsplit, t.order, t.persistent, t.cell_scale = int(xsplit), int(order), \
+            int(persistent), float(cell_scale)
+        self.ctx._check(lib.sr_plan_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self.ctx._check(lib.sr_plan_get_tuning(self._h, ctypes.byref(t)))
+        return _tuning_dict(t)
+
+    def autotune(self, reps: int = 3):
+        t = Tuning()
+        ms = ctypes.c_double()
+        self.ctx._check(lib.sr_plan_autotune(self._h, int(reps), ctypes.byref(t),
+                                             ctypes.byref(ms)))
+        return _tuning_dict(t), float(ms.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """sr_server: continuous batching of stream-kick-stream requests.
+
+    submit() takes numpy host arrays; the caller keeps them alive until the
+    request completes (output arrays should be pinned, see pinned_empty)."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int, r_max: float, eps: float,
+                 poly, cell: float, xsplit: int = 2, order: int = 1, persistent: int = 0):
+        self.ctx = ctx
+        cfg = ServerConfig()
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.max_slots = int(max_slots)
+        cfg.r_max, cfg.eps = float(r_max), float(eps)
+        for k in range(6):
+            cfg.poly[k] = float(poly[k])
+        cfg.cell = float(cell)
+        cfg.tuning.xsplit, cfg.tuning.order = int(xsplit), int(order)
+        cfg.tuning.persistent, cfg.tuning.cell_scale = int(persistent), 1.0
+        h = ctypes.c_void_p()
+        ctx._bind_stream()
+        ctx._check(lib.sr_server_create(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, L: float, steps: int, dt: float, pos64, vel, mass, out_pos, out_vel) -> int:
+        import numpy as np
+        n = int(mass.shape[0])
+        arrs = [np.ascontiguousarray(pos64[:, d], dtype=np.float64) for d in range(3)]
+        arrs += [np.ascontiguousarray(vel[:, d], dtype=np.float32) for d in range(3)]
+        arrs += [np.ascontiguousarray(mass, dtype=np.float32)]
+        for a in list(out_pos) + list(out_vel):
+            assert a.flags["C_CONTIGUOUS"] and a.shape[0] == n
+        r = Request()
+        r.n, r.len, r.steps, r.dt = n, float(L), int(steps), float(dt)
+        r.x, r.y, r.z, r.vx, r.vy, r.vz, r.mass = (a.ctypes.data for a in arrs)
+        r.out_x, r.out_y, r.out_z = (a.ctypes.data for a in out_pos)
+        r.out_vx, r.out_vy, r.out_vz = (a.ctypes.data for a in out_vel)
+        rid = ctypes.c_int64()
+        self.ctx._bind_stream()
+        self.ctx._check(lib.sr_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._keep[int(rid.value)] = (arrs, out_pos, out_vel)
+        return int(rid.value)
+
+    def tick(self) -> int:
+        a = ctypes.c_int()
+        self.ctx._bind_stream()
+        self.ctx._check(lib.sr_server_tick(self._h, ctypes.byref(a)))
+        return int(a.value)
+
+    def poll(self) -> list[int]:
+        ids = (ctypes.c_int64 * 256)()
+        n = ctypes.c_int()
+        out = []
+        while True:
+            self.ctx._check(lib.sr_server_poll(self._h, ids, 256, ctypes.byref(n)))
+            out += [int(ids[k]) for k in range(n.value)]
+            if n.value < 256:
+                break
+        for rid in out:
+            self._keep.pop(rid, None)
+        return out
+
+    def cancel(self, rid: int):
+        self.ctx._check(lib.sr_server_cancel(self._h, int(rid)))
+
+    def info(self) -> dict:
+        i = ServerInfo()
+        self.ctx._check(lib.sr_server_info_get(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sr_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_PINNED = {}
+
+
+def pinned_empty(shape, dtype):
+    """Page-locked host numpy array backed by a pinned torch tensor (kept
+    alive for the process; use for serving result buffers)."""
+    import numpy as np
+    tdt = {np.float64: torch.float64, np.float32: torch.float32}[np.dtype(dtype).type]
+    t = torch.empty(shape, dtype=tdt, pin_memory=True)
+    a = t.numpy()
+    _PINNED[a.ctypes.data] = t
+    return a
+
+
+def pinned_release(a) -> None:
+    _PINNED.pop(a.ctypes.data, None)

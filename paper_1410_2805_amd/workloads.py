@@ -89,7 +89,12 @@ def uniform(n: int, L: float, seed: int) -> Particles:
 
 
 def zeldovich(ngrid: int, L: float, seed: int, rms: float = 0.5) -> Particles:
-    """ngrid^3 particles on the lattice q = (i + 1/2) * L/ngrid, displaced by
+    """Float32 particles of ``zeldovich_pos64``."""
+    return _soa(zeldovich_pos64(ngrid, L, seed, rms), L)
+
+
+def zeldovich_pos64(ngrid: int, L: float, seed: int, rms: float = 0.5) -> np.ndarray:
+    """(ngrid^3, 3) float64 positions in [0, L)^3: ngrid^3 particles on the lattice q = (i + 1/2) * L/ngrid, displaced by
     a Zel'dovich displacement psi with del.psi = -delta.
 
     delta is a Gaussian random field with P(k) ~ k^-2 for 0 < |k| <= pi/h
@@ -129,7 +134,9 @@ def zeldovich(ngrid: int, L: float, seed: int, rms: float = 0.5) -> Particles:
     idx = np.arange(ngrid, dtype=np.float64)
     qx, qy, qz = np.meshgrid(idx, idx, idx, indexing="ij")
     q = (np.stack([qx.reshape(-1), qy.reshape(-1), qz.reshape(-1)], axis=1) + 0.5) * h
-    return _soa(q + psi, L)
+    pos = np.mod(q + psi, L)
+    pos[pos >= L] -= L
+    return pos
 
 
 def _powerlaw_counts(rng, total: int, lo: float, hi: float, slope: float) -> np.ndarray:
@@ -236,7 +243,8 @@ def batch_specs(nboxes: int = 64, seed: int = 4, lo: int = 16 ** 3, hi: int = 96
     specs = []
     for b, nb in enumerate(ns):
         kind = "uniform" if b % 2 == 0 else "clustered"
-        specs.append(BoxSpec(int(nb), float(nb) ** (1.0 / 3.0), kind, int(seed * 1000 + b)))
+        side = float(np.float32(float(nb) ** (1.0 / 3.0)))  # exact in float32
+        specs.append(BoxSpec(int(nb), side, kind, int(seed * 1000 + b)))
     return specs
 
 

@@ -98,7 +98,7 @@ def test_xsplit_settings(sr, ctx, poly, xsplit):
     including boxes with only 3 chaining cells per axis."""
     before = ctx.get_tuning()["xsplit"]
     try:
-        ctx.set_tuning(xsplit)
+        ctx.set_tuning(xsplit=xsplit)
         for (n, L, cell, seed) in ((5000, 17.0, 3.0, 40 + xsplit), (900, 9.5, 3.0, 50 + xsplit),
                                    (3000, 14.0, 4.5, 60 + xsplit)):
             p = W.uniform(n, L, seed)
@@ -109,9 +109,28 @@ def test_xsplit_settings(sr, ctx, poly, xsplit):
         a, _ = _gpu_force(sr, ctx, q, 3.0, poly)
         check_accel(a, _ref(q, poly), "xsplit %d open" % xsplit)
     finally:
-        ctx.set_tuning(before)
+        ctx.set_tuning(xsplit=before)
     with pytest.raises(sr.SRError):
-        ctx.set_tuning(5)
+        ctx.set_tuning(xsplit=5)
+
+
+@pytest.mark.parametrize("order,persistent", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_item_order_and_persistent(sr, ctx, poly, order, persistent):
+    """Work-item order (cell order / decreasing cost) and the persistent
+    variant change scheduling only: results are bitwise those of the default
+    setting, and match the oracle."""
+    before = ctx.get_tuning()
+    p = W.nfw_share(25000, 27.0, 90, periodic=True, halo_cap=5000)
+    p.m = np.random.default_rng(91).uniform(0.5, 2.0, p.n).astype(np.float32)
+    try:
+        ctx.set_tuning(order=0, persistent=0)
+        a0, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+        ctx.set_tuning(order=order, persistent=persistent)
+        a1, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    finally:
+        ctx.set_tuning(**before)
+    assert np.array_equal(a0, a1)
+    check_accel(a1, _ref(p, poly), "order %d persistent %d" % (order, persistent))
 
 
 def test_determinism_and_momentum(sr, ctx, poly):

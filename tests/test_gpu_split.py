@@ -1,0 +1,115 @@
+"""Precision form: split (cell + float32 offset) coordinates against the
+FP64-master oracle, next to the global-float32 path on the same box."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1410_2805_amd import gridfit
+from paper_1410_2805_amd import workloads as W
+from tests.parity import accel_np, check_accel
+
+pytestmark = pytest.mark.gpu
+
+R_MAX, EPS = 3.0, 0.1
+
+
+@pytest.fixture(scope="module")
+def sr():
+    from paper_1410_2805_amd import sr as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(sr):
+    c = sr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def poly():
+    return gridfit.poly_coeffs()
+
+
+def _dev64(pos):
+    return [torch.from_numpy(np.ascontiguousarray(pos[:, d])).to("cuda:0") for d in range(3)]
+
+
+def test_round_trip(sr, ctx):
+    L, cell = 40.0, 3.0
+    pos = np.random.default_rng(1).random((50000, 3)) * L
+    pos[:5] = [[0.0, 0.0, 0.0], [L - 1e-9, 3.0, 39.0], [13.3333333333, 26.6666666667, 0.5],
+               [3.0769230769230766, 6.153846153846153, 9.23076923076923], [1e-300, 1e-5, 20.0]]
+    box = sr.Box.make(L)
+    x, y, z = _dev64(pos)
+    c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+    bx, by, bz = sr.sr_split_to_f64(ctx, c3, ox, oy, oz, box, cell)
+    ctx.sync()
+    back = torch.stack([bx, by, bz], 1).cpu().numpy()
+    h = L / 13
+    d = np.abs(back - pos)
+    d = np.minimum(d, L - d)
+    assert d.max() <= 0.5 * np.spacing(np.float32(h)) * 1.01
+    o = torch.stack([ox, oy, oz], 1).cpu().numpy()
+    assert o.min() >= 0 and o.max() <= h * (1 + 1e-6)
+    c = c3.cpu().numpy()
+    for k, sh in enumerate((0, 10, 20)):
+        ck = (c >> sh) & 1023
+        assert ck.max() < 13
+    with pytest.raises(sr.SRError):
+        sr.sr_split_from_f64(ctx, x, y, z, sr.Box.make(L, periodic=False), cell)
+    bad = x.clone()
+    bad[7] = L
+    sr.sr_split_from_f64(ctx, bad, y, z, box, cell)
+    with pytest.raises(sr.SRError):
+        ctx.sync()
+
+
+@pytest.mark.parametrize("xsplit", [1, 2, 3])
+def test_split_force_small_boxes(sr, ctx, poly, xsplit):
+    before = ctx.get_tuning()["xsplit"]
+    try:
+        ctx.set_tuning(xsplit=xsplit)
+        for (n, L, cell, seed) in ((6000, 18.0, 3.0, 1), (900, 9.5, 3.0, 2), (3000, 14.0, 4.5, 3)):
+            pos = np.random.default_rng(seed).random((n, 3)) * L
+            m = np.random.default_rng(seed + 9).uniform(0.5, 2.0, n).astype(np.float32)
+            box = sr.Box.make(L)
+            x, y, z = _dev64(pos)
+            c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+            tm = torch.from_numpy(m).to("cuda:0")
+            ax, ay, az, _ = sr.sr_force_split(ctx, c3, ox, oy, oz, tm, box, cell, R_MAX, EPS, poly)
+            ctx.sync()
+            ref = O.force(pos[:, 0], pos[:, 1], pos[:, 2], m, L, R_MAX, EPS,
+                          poly.astype(np.float64))
+            check_accel(accel_np(ax, ay, az), ref, "split xsplit=%d L=%g" % (xsplit, L))
+    finally:
+        ctx.set_tuning(xsplit=before)
+
+
+@pytest.mark.slow
+def test_split_beats_global_float32_at_L128(sr, ctx, poly):
+    """The 128^3 Zel'dovich box with float64 master positions: split
+    coordinates track the FP64 oracle more closely than global float32
+    coordinates (which round positions to ulp(128)/2 ~ 3.8e-6)."""
+    L, cell = 128.0, 3.0
+    pos = W.zeldovich_pos64(128, L, 2)
+    n = pos.shape[0]
+    m = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    box = sr.Box.make(L)
+    x, y, z = _dev64(pos)
+    c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+    sa = sr.sr_force_split(ctx, c3, ox, oy, oz, m, box, cell, R_MAX, EPS, poly)
+    p32 = pos.astype(np.float32)
+    p32[p32 >= np.float32(L)] = 0
+    t32 = [torch.from_numpy(np.ascontiguousarray(p32[:, d])).to("cuda:0") for d in range(3)]
+    ga = sr.sr_force(ctx, *t32, m, box, cell, R_MAX, EPS, poly)
+    ctx.sync()
+    tg = np.sort(np.random.default_rng(5).choice(n, 2048, replace=False))
+    ref = O.force(pos[:, 0], pos[:, 1], pos[:, 2], np.ones(n), L, R_MAX, EPS,
+                  poly.astype(np.float64), targets=tg)
+    st_split = check_accel(accel_np(*sa[:3])[tg], ref, "split L=128")
+    st_glob = check_accel(accel_np(*ga[:3])[tg], ref, "global f32 L=128")
+    print("relRMS vs FP64 masters: split %.3e, global float32 %.3e" % (st_split["rel_rms"],
+                                                                       st_glob["rel_rms"]))
+    assert st_split["rel_rms"] < st_glob["rel_rms"]
