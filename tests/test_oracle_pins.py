@@ -277,3 +277,19 @@ def test_sks_free_streaming_and_reversibility():
     dpos -= 9.0 * np.round(dpos / 9.0)
     assert np.max(np.abs(dpos)) < 1e-10 and np.max(np.abs(vb - vel)) < 1e-10
     assert np.allclose((m[:, None] * w).sum(0), (m[:, None] * vel).sum(0), atol=1e-10)
+
+
+def test_sks_one_step_closed_form():
+    """Two particles at rest, p = 0, eps -> 0: one stream-kick-stream step
+    leaves the first half stream idle, kicks each by dt m / r^2 towards the
+    other (Newton) and streams it by half the new velocity."""
+    L, r, dt = 20.0, 1.25, 0.01
+    pos = np.array([[5.0, 7.0, 9.0], [5.0 + r, 7.0, 9.0]])
+    vel = np.zeros((2, 3))
+    m = np.array([1.0, 3.0])
+    p1, v1, a1 = O.sks(pos, vel, m, L, 3.0, 1e-22, ZERO, dt)
+    assert a1[0, 0] == pytest.approx(3.0 / r ** 2, rel=1e-12)
+    assert a1[1, 0] == pytest.approx(-1.0 / r ** 2, rel=1e-12)
+    assert v1[0, 0] == pytest.approx(dt * 3.0 / r ** 2, rel=1e-12)
+    assert p1[0, 0] == pytest.approx(5.0 + 0.5 * dt * dt * 3.0 / r ** 2, rel=1e-14)
+    assert np.all(v1[:, 1:] == 0) and np.all(p1[:, 1:] == pos[:, 1:])
