@@ -186,6 +186,28 @@ __device__ __forceinline__ void stage_tile(float4 *tile, const Stencil &st,
     }
 }
 
+// Loads sources [g0, g0 + cnt) of the stencil (cnt <= kTile) into registers,
+// entry q = lane + 64 k in pre[k]; entries past cnt are far, massless padding.
+__device__ __forceinline__ void load_tile(float4 (&pre)[kTile / 64], const Stencil &st,
+                                          const float4 *__restrict__ sorted, int g0, int cnt,
+                                          int lane, int &p)
+{
+#pragma unroll
+    for (int k = 0; k < kTile / 64; ++k) {
+        const int q = lane + 64 * k;
+        float4 v = make_float4(kFar, kFar, kFar, 0.f);
+        if (q < cnt) {
+            const int gi = g0 + q;
+            while (gi >= st.pbeg[p + 1])
+                ++p;
+            const float4 s = sorted[st.psrc[p] + (gi - st.pbeg[p])];
+            const float4 sh = st.psh[p];
+            v = make_float4(s.x + sh.x, s.y + sh.y, s.z + sh.z, s.w);
+        }
+        pre[k] = v;
+    }
+}
+
 // One tile of pair interactions for one lane: sources src[0 .. cnt) (cnt a
 // multiple of 4), target (xi, yi, zi); partial sums into tx, ty, tz.
 template <bool kUniformMass>
@@ -256,13 +278,27 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
     float acx = 0.f, acy = 0.f, acz = 0.f;
     if (__any(has_target && !pas)) {
         const int total = st.pbeg[kMaxPieces];
+        // a pass stages `cap` sources (a multiple of the 4 S slice quantum, so
+        // that padding stays inside the tile); the next pass's global loads
+        // are issued before the current pass computes
         const int quantum = 4 * S;
+        const int cap = kTile / quantum * quantum;
+        float4 pre[kTile / 64];
         int p = 0;
-        for (int g0 = 0; g0 < total; g0 += kTile) {
-            const int cnt = total - g0 < kTile ? total - g0 : kTile;
+        int g0 = 0;
+        int cnt = total < cap ? total : cap;
+        load_tile(pre, st, sorted, g0, cnt, lane, p);
+        for (;;) {
             const int cntp = (cnt + quantum - 1) / quantum * quantum;
-            stage_tile(tile, st, sorted, g0, cnt, cntp, lane, p);
+#pragma unroll
+            for (int k = 0; k < kTile / 64; ++k)
+                if (lane + 64 * k < cntp)
+                    tile[lane + 64 * k] = pre[k];
             __syncthreads();
+            const int g1 = g0 + cnt;
+            const int cnt1 = total - g1 < cap ? total - g1 : cap;
+            if (cnt1 > 0)
+                load_tile(pre, st, sorted, g1, cnt1, lane, p);
             const int slice = cntp / S;
             const float4 *src = tile + (has_target ? part : 0) * slice;
             float tx = 0.f, ty = 0.f, tz = 0.f;
@@ -274,6 +310,10 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
             acy += ty;
             acz += tz;
             __syncthreads();
+            if (cnt1 <= 0)
+                break;
+            g0 = g1;
+            cnt = cnt1;
         }
         if (uniform) {
             acx *= pt.w;
@@ -317,7 +357,7 @@ __global__ __launch_bounds__(64) void k_force(Batch B, const int4 *__restrict__ 
                                               const int *__restrict__ perm,
                                               const int *__restrict__ mass_mixed, ForceParams fp)
 {
-    __shared__ float4 tile[kTile + 4 * kMaxSplit];
+    __shared__ float4 tile[kTile];
     __shared__ Stencil st;
     const int pos = item_position(blockIdx.x);
     if (pos >= *n_items)
@@ -335,7 +375,7 @@ __global__ __launch_bounds__(64) void k_force_persistent(Batch B, const int4 *__
                                                          const int *__restrict__ mass_mixed,
                                                          ForceParams fp, int *__restrict__ queue)
 {
-    __shared__ float4 tile[kTile + 4 * kMaxSplit];
+    __shared__ float4 tile[kTile];
     __shared__ Stencil st;
     __shared__ int next;
     const int n = *n_items;
@@ -362,7 +402,7 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
                                                    int *__restrict__ per_target,
                                                    unsigned long long *__restrict__ stats)
 {
-    __shared__ float4 tile[kTile + 4 * kMaxSplit];
+    __shared__ float4 tile[kTile];
     __shared__ Stencil st;
     const int lane = threadIdx.x;
     const int it = blockIdx.x;

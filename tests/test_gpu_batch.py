@@ -34,7 +34,7 @@ def poly():
     return gridfit.poly_coeffs()
 
 
-def _boxes():
+def _boxes(tiny=True):
     out = []
     u = W.uniform(4096, 16.0, 1)
     out.append((u, 3.0))
@@ -42,8 +42,9 @@ def _boxes():
     out.append((c, 3.0))
     o = W.nfw_share(9000, 21.0, 3, skin=3.0)
     out.append((o, 3.0))
-    t = W.uniform(857, 9.5, 4)
-    out.append((t, 3.0))
+    if tiny:  # only 3 cells per axis: invalid at a coarser cell scale
+        t = W.uniform(857, 9.5, 4)
+        out.append((t, 3.0))
     e = W.Particles(*(np.zeros(0, np.float32) for _ in range(4)), 12.0)
     out.append((e, 3.0))
     m = W.uniform(2197, 13.0, 5)
@@ -90,7 +91,7 @@ def _ref(p, poly):
                                     dict(xsplit=3, order=1, persistent=1, cell_scale=1.0),
                                     dict(xsplit=2, order=0, persistent=0, cell_scale=1.25)])
 def test_batch_matches_single_boxes(sr, ctx, poly, tuning):
-    boxes = _boxes()
+    boxes = _boxes(tiny=tuning["cell_scale"] == 1.0)
     dev = _plan_inputs(sr, boxes)
     mom = torch.zeros(3 * len(boxes), dtype=torch.float64, device="cuda:0")
     plan = sr.Plan(ctx, dev, R_MAX, EPS, poly, momentum=mom)
