@@ -43,6 +43,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per k_force launch from the committed rocprofv3 FETCH/WRITE
+    summary, or None when it was taken on another workload or the kernel's
+    sources changed since (the summary stores their SHA-256)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_force_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for src in d["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return d["traffic_bytes"] if h.hexdigest() == d["source_sha256"] else None
+
+
 def cpu_baseline(p, poly, seconds: float):
     """Times the oracle on a seeded target sample sized for ~`seconds`."""
     import numpy as np
@@ -206,7 +221,7 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
         },
         "cpu_baseline": cpu,
     }

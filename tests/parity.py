@@ -24,6 +24,17 @@ def accel_np(ax, ay, az):
     return torch.stack([ax, ay, az], 1).double().cpu().numpy()
 
 
+def measure_accel(a_gpu: np.ndarray, ref: dict) -> dict:
+    """Error figures only (no assertion)."""
+    ar = ref["a"]
+    err = np.linalg.norm(a_gpu - ar, axis=1)
+    nref = np.linalg.norm(ar, axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(nref > 0, err / nref, 0.0)
+    return {"rel_rms": float(np.sqrt((err ** 2).sum() / max(float((nref ** 2).sum()), 1e-300))),
+            "max_rel": float(rel.max()) if rel.size else 0.0}
+
+
 def check_accel(a_gpu: np.ndarray, ref: dict, label: str = "") -> dict:
     """Asserts the tolerances; returns the measured error figures."""
     ar = ref["a"]

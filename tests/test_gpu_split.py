@@ -7,7 +7,7 @@ import torch
 from oracle import oracle as O
 from paper_1410_2805_amd import gridfit
 from paper_1410_2805_amd import workloads as W
-from tests.parity import accel_np, check_accel
+from tests.parity import accel_np, check_accel, measure_accel
 
 pytestmark = pytest.mark.gpu
 
@@ -90,8 +90,9 @@ def test_split_force_small_boxes(sr, ctx, poly, xsplit):
 @pytest.mark.slow
 def test_split_beats_global_float32_at_L128(sr, ctx, poly):
     """The 128^3 Zel'dovich box with float64 master positions: split
-    coordinates track the FP64 oracle more closely than global float32
-    coordinates (which round positions to ulp(128)/2 ~ 3.8e-6)."""
+    coordinates meet the tolerance against the FP64 oracle on the masters and
+    track it more closely than global float32 coordinates, whose inputs are
+    already rounded by up to ulp(128)/2 ~ 3.8e-6 (reported, not asserted)."""
     L, cell = 128.0, 3.0
     pos = W.zeldovich_pos64(128, L, 2)
     n = pos.shape[0]
@@ -109,7 +110,7 @@ def test_split_beats_global_float32_at_L128(sr, ctx, poly):
     ref = O.force(pos[:, 0], pos[:, 1], pos[:, 2], np.ones(n), L, R_MAX, EPS,
                   poly.astype(np.float64), targets=tg)
     st_split = check_accel(accel_np(*sa[:3])[tg], ref, "split L=128")
-    st_glob = check_accel(accel_np(*ga[:3])[tg], ref, "global f32 L=128")
+    st_glob = measure_accel(accel_np(*ga[:3])[tg], ref)
     print("relRMS vs FP64 masters: split %.3e, global float32 %.3e" % (st_split["rel_rms"],
                                                                        st_glob["rel_rms"]))
     assert st_split["rel_rms"] < st_glob["rel_rms"]
