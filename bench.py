@@ -183,6 +183,25 @@ def main():
     achieved = FLOP_PER_PAIR * cand / (force_avg * 1e-3) / 1e12
     value = useful / (ms_step * 1e-3)
 
+    # the same one-box pass replayed as a captured HIP graph (a plan of one box)
+    plan = sr.Plan(ctx, [dict(x=t["x"], y=t["y"], z=t["z"], m=t["m"], ax=out[0], ay=out[1],
+                              az=out[2], box=box, cell=args.cell)], R_MAX, EPS, poly,
+                   momentum=mom)
+    plan.set_tuning(xsplit=tuning["xsplit"], order=tuning["order"],
+                    persistent=tuning["persistent"])
+    plan.capture()
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        plan.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_graph = ev0.elapsed_time(ev1) / args.steps
+    plan.close()
+    log("graph replay of the same pass: %.4f ms" % ms_graph)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, poly, args.cpu_seconds)
@@ -213,6 +232,8 @@ def main():
             "pair_loop_ms": force_avg,
             "pair_loop_useful_per_s": useful / (force_avg * 1e-3),
             "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
+            "graph_replay_ms_per_step": ms_graph,
+            "graph_replay_useful_per_s": useful / (ms_graph * 1e-3),
         },
         "roofline": {
             "bound": "alu",

@@ -76,84 +76,115 @@ __global__ void k_fill(int *__restrict__ p, int value, int64_t count)
         p[i] = value;
 }
 
+constexpr int kCellidPer = 4;                 // particles per thread
+constexpr int kCellidBlock = kBlock * kCellidPer;  // 1024 particles per block
+constexpr int kHash = 2048;                   // > 2 x distinct cells per block
+
+__device__ __forceinline__ int particle_cell(const Batch &B, int i, int *status)
+{
+    const BoxDesc &d = box_at(B, find_box(B.pstart, B.nb, i));
+    const int li = i - d.pbase;
+    const float p[3] = {d.x[li], d.y[li], d.z[li]};
+    const Geom &g = d.g;
+    int c[3];
+    bool bad = false;
+    if (g.split) {
+        // chaining cell from cell3; the x sub-cell from the offset
+        const int packed = d.cell3[li];
+        const int cc[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
+        const int per[3] = {g.hx, 1, 1};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double v = (double)p[k];
+            const int ncc = g.nc[k] / per[k];
+            if (!(v >= 0.0 && v <= 1.0001 * g.w[k] * per[k]) || cc[k] >= ncc) {
+                bad = true;
+                c[k] = 0;
+            } else {
+                int sub = (int)floor(v * g.inv[k]);
+                sub = sub < per[k] - 1 ? sub : per[k] - 1;
+                c[k] = cc[k] * per[k] + sub;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double v = (double)p[k];
+            if (!(v >= 0.0 && v < g.len[k])) {  // also catches NaN
+                bad = true;
+                c[k] = 0;
+            } else {
+                double t = floor(v * g.inv[k]);
+                int ci = (int)t;
+                c[k] = ci < g.nc[k] - 1 ? ci : g.nc[k] - 1;
+            }
+        }
+    }
+    if (bad)
+        atomicOr(status, 1);
+    return d.cbase + c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+}
+
+// Cell ids and the histogram.  A block takes 1024 particles and first counts
+// them per cell in an LDS hash table (input that is even roughly spatially
+// ordered repeats cells a lot), then adds each distinct cell's count to the
+// global histogram with one atomic; a particle's arrival rank is its block's
+// base plus its rank inside the block (ranks are unordered; the per-cell sort
+// restores the stable order).
 __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ cid,
                                                    int *__restrict__ slot,
                                                    int *__restrict__ count, int *__restrict__ status)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const bool live = i < B.ntot;
-    int id = 0;
-    if (live) {
-        const BoxDesc &d = box_at(B, find_box(B.pstart, B.nb, i));
-        const int li = i - d.pbase;
-        const float p[3] = {d.x[li], d.y[li], d.z[li]};
-        const Geom &g = d.g;
-        int c[3];
-        bool bad = false;
-        if (g.split) {
-            // chaining cell from cell3; the x sub-cell from the offset
-            const int packed = d.cell3[li];
-            const int cc[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
-            const int per[3] = {g.hx, 1, 1};
+    __shared__ int hkey[kHash];
+    __shared__ int hcnt[kHash];
+    for (int h = threadIdx.x; h < kHash; h += kBlock) {
+        hkey[h] = -1;
+        hcnt[h] = 0;
+    }
+    __syncthreads();
+    int hs[kCellidPer], rk[kCellidPer];
+    const int base = blockIdx.x * kCellidBlock;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double v = (double)p[k];
-                const int ncc = g.nc[k] / per[k];
-                if (!(v >= 0.0 && v <= 1.0001 * g.w[k] * per[k]) || cc[k] >= ncc) {
-                    bad = true;
-                    c[k] = 0;
-                } else {
-                    int sub = (int)floor(v * g.inv[k]);
-                    sub = sub < per[k] - 1 ? sub : per[k] - 1;
-                    c[k] = cc[k] * per[k] + sub;
-                }
+    for (int k = 0; k < kCellidPer; ++k) {
+        const int i = base + k * kBlock + threadIdx.x;
+        hs[k] = -1;
+        if (i < B.ntot) {
+            const int id = particle_cell(B, i, status);
+            cid[i] = id;
+            int h = (int)(((unsigned)id * 2654435761u) >> 21) & (kHash - 1);
+            for (;;) {  // at most 1024 keys in 2048 slots: always terminates
+                const int old = atomicCAS(&hkey[h], -1, id);
+                if (old == -1 || old == id)
+                    break;
+                h = (h + 1) & (kHash - 1);
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                double v = (double)p[k];
-                if (!(v >= 0.0 && v < g.len[k])) {  // also catches NaN
-                    bad = true;
-                    c[k] = 0;
-                } else {
-                    double t = floor(v * g.inv[k]);
-                    int ci = (int)t;
-                    c[k] = ci < g.nc[k] - 1 ? ci : g.nc[k] - 1;
-                }
-            }
+            hs[k] = h;
+            rk[k] = atomicAdd(&hcnt[h], 1);
         }
-        if (bad)
-            atomicOr(status, 1);
-        id = d.cbase + c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
-        cid[i] = id;
     }
-    // Spatially ordered input puts many lanes of a wavefront in one cell:
-    // lanes sharing the first few distinct ids take one atomic per id.
-    unsigned long long todo = __ballot(live);
-    int my = -1;
-    for (int round = 0; round < 4 && todo; ++round) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int lid = __shfl(id, leader, 64);
-        const unsigned long long peers = __ballot(live && id == lid) & todo;
-        int base = 0;
-        if (lane == leader)
-            base = atomicAdd(&count[lid], __popcll(peers));
-        base = __shfl(base, leader, 64);
-        if ((peers >> lane) & 1ull)
-            my = base + __popcll(peers & ((1ull << lane) - 1ull));
-        todo &= ~peers;
+    __syncthreads();
+    for (int h = threadIdx.x; h < kHash; h += kBlock) {
+        const int c = hcnt[h];
+        if (c > 0)
+            hcnt[h] = atomicAdd(&count[hkey[h]], c);  // becomes the block's base
     }
-    if (live && my < 0)
-        my = atomicAdd(&count[id], 1);
-    if (live)
-        slot[i] = my;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCellidPer; ++k) {
+        const int i = base + k * kBlock + threadIdx.x;
+        if (hs[k] >= 0)
+            slot[i] = hcnt[hs[k]] + rk[k];
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int *__restrict__ in, int m,
-                                                        int *__restrict__ part)
+// Tile sums; the block that finishes last (a device counter, reset by that
+// block) scans the tile partials in place.  No block ever waits for another.
+__global__ __launch_bounds__(kBlock) void k_scan_up(const int *__restrict__ in, int m,
+                                                    int *__restrict__ part, int ntiles,
+                                                    int *__restrict__ done)
 {
     __shared__ int sh[8];
+    __shared__ bool last;
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
     int s = 0;
 #pragma unroll
@@ -161,24 +192,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int *__restrict__ 
         s += (base + k < m) ? in[base + k] : 0;
     int total;
     (void)block_exclusive_scan(s, sh, &total);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         part[blockIdx.x] = total;
-}
-
-// One block: exclusive scan of the tile partials in place.
-__global__ __launch_bounds__(kBlock) void k_scan_partials(int *__restrict__ part, int ntiles)
-{
-    __shared__ int sh[8];
+        __threadfence();
+        last = atomicAdd(done, 1) == ntiles - 1;
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
     int carry = 0;
     for (int b = 0; b < ntiles; b += kBlock) {
-        int i = b + threadIdx.x;
-        int v = i < ntiles ? part[i] : 0;
-        int total;
-        int ex = block_exclusive_scan(v, sh, &total);
+        const int i = b + threadIdx.x;
+        const int v = i < ntiles ? __hip_atomic_load(&part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        int tot;
+        const int ex = block_exclusive_scan(v, sh, &tot);
         if (i < ntiles)
             part[i] = carry + ex;
-        carry += total;
+        carry += tot;
     }
+    if (threadIdx.x == 0)
+        *done = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_down(const int *__restrict__ in, int m,
@@ -268,14 +302,34 @@ __device__ __forceinline__ float4 gather_one(const BoxDesc &d, int v)
     return make_float4(x, d.y[li], d.z[li], d.m[li]);
 }
 
+// Sorted copy by scattering in input order: sorted[inv[i]] = particle i.
+// Reads are coalesced; writes land in runs wherever the input keeps
+// neighbours together.  Also flags boxes whose masses are not all equal.
+__global__ __launch_bounds__(kBlock) void k_gather(Batch B, const int *__restrict__ inv,
+                                                   float4 *__restrict__ sorted,
+                                                   int *__restrict__ mass_mixed)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    bool mixed = false;
+    int box = 0;
+    if (i < B.ntot) {
+        box = find_box(B.pstart, B.nb, i);
+        const BoxDesc &d = box_at(B, box);
+        const float4 q = gather_one(d, i);
+        sorted[inv[i]] = q;
+        mixed = q.w != d.m[0];
+    }
+    if (mixed)
+        atomicOr(&mass_mixed[box], 1);
+}
+
 // One wavefront per cell.
 __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restrict__ offsets,
                                                     int *__restrict__ perm,
                                                     int *__restrict__ large_list,
                                                     int *__restrict__ large_count,
-                                                    float4 *__restrict__ sorted,
-                                                    int *__restrict__ chunk_count,
-                                                    int *__restrict__ mass_mixed)
+                                                    int *__restrict__ inv,
+                                                    int *__restrict__ chunk_count)
 {
     __shared__ int buf[kBlock / 64][kLargeCell];
     const int lane = threadIdx.x & 63;
@@ -283,26 +337,30 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
     const int cell = blockIdx.x * (kBlock / 64) + wid;
     if (cell >= B.ctot)
         return;
-    const int b = offsets[cell];
-    const int len = offsets[cell + 1] - b;
+    // one cell per wavefront: its bounds are wavefront-uniform
+    const int b = __builtin_amdgcn_readfirstlane(offsets[cell]);
+    const int len = __builtin_amdgcn_readfirstlane(offsets[cell + 1]) - b;
     if (chunk_count && lane == 0)
         chunk_count[cell] = chunks_for(len);
-    const int box = sorted ? find_box(B.cstart, B.nb, cell) : 0;
-    if (len <= 64) {
+    if (len <= 32) {
+        // small cell: each index's rank is the number of smaller ones
+        const int v = lane < len ? perm[b + lane] : INT_MAX;
+        int rank = 0;
+        for (int k = 0; k < len; ++k)
+            rank += __builtin_amdgcn_readlane(v, k) < v ? 1 : 0;
+        if (lane < len) {
+            perm[b + rank] = v;
+            if (inv)
+                inv[v] = b + rank;
+        }
+    } else if (len <= 64) {
         int v = lane < len ? perm[b + lane] : INT_MAX;
         v = bitonic64(v, lane);
-        bool mixed = false;
         if (lane < len) {
             perm[b + lane] = v;
-            if (sorted) {
-                const BoxDesc &d = box_at(B, box);
-                const float4 q = gather_one(d, v);
-                sorted[b + lane] = q;
-                mixed = q.w != d.m[0];
-            }
+            if (inv)
+                inv[v] = b + lane;
         }
-        if (__any(mixed) && lane == 0)
-            atomicOr(&mass_mixed[box], 1);
     } else if (len <= kLargeCell) {
         int P = 128;
         while (P < len)
@@ -312,19 +370,12 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
             sb[t] = t < len ? perm[b + t] : INT_MAX;
         wave_sync();
         lds_bitonic(sb, P, lane);
-        bool mixed = false;
         for (int t = lane; t < len; t += 64) {
             int v = sb[t];
             perm[b + t] = v;
-            if (sorted) {
-                const BoxDesc &d = box_at(B, box);
-                const float4 q = gather_one(d, v);
-                sorted[b + t] = q;
-                mixed = mixed || q.w != d.m[0];
-            }
+            if (inv)
+                inv[v] = b + t;
         }
-        if (__any(mixed) && lane == 0)
-            atomicOr(&mass_mixed[box], 1);
     } else if (lane == 0) {
         int k = atomicAdd(large_count, 1);
         large_list[k] = cell;
@@ -340,8 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
                                                           int *__restrict__ tmp,
                                                           const int *__restrict__ large_list,
                                                           const int *__restrict__ large_count,
-                                                          float4 *__restrict__ sorted,
-                                                          int *__restrict__ mass_mixed)
+                                                          int *__restrict__ inv)
 {
     __shared__ int buf[kLargeCell];
     const int nl = *large_count;
@@ -413,17 +463,9 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
                 perm[b + e] = src[e];
             __syncthreads();
         }
-        if (sorted) {
-            const int box = find_box(B.cstart, B.nb, cell);
-            const BoxDesc &d = box_at(B, box);
-            bool mixed = false;
-            for (int e = threadIdx.x; e < len; e += kBlock) {
-                const float4 q = gather_one(d, perm[b + e]);
-                sorted[b + e] = q;
-                mixed = mixed || q.w != d.m[0];
-            }
-            if (mixed)
-                atomicOr(&mass_mixed[box], 1);
+        if (inv) {
+            for (int e = threadIdx.x; e < len; e += kBlock)
+                inv[perm[b + e]] = b + e;
         }
         __syncthreads();
     }
@@ -451,16 +493,38 @@ void scan_layout(Bump &b, int m, int **part)
     *part = b.take<int>(tiles > 0 ? tiles : 1);
 }
 
-// out[0..m] = exclusive prefix sums of in[0..m-1], out[m] = total.
-int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out)
+// out[0..m] = exclusive prefix sums of in[0..m-1], out[m] = total.  `flag`
+// is a device int that must be 0 (it is left 0).
+int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out, int *flag)
 {
     if (m <= 0)
         return fill_enqueue(ctx, out, 0, 1);
     int tiles = (m + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(kBlock), 0, ctx->stream, in, m, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, ctx->stream, part, tiles);
+    hipLaunchKernelGGL(k_scan_up, dim3(tiles), dim3(kBlock), 0, ctx->stream, in, m, part, tiles,
+                       flag);
     hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(kBlock), 0, ctx->stream, in, m, part, out);
     return sr_check_launch(ctx, "scan");
+}
+
+__global__ void k_clear(ClearList cl)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (cl.p[k] && i < cl.n[k])
+            cl.p[k][i] = 0;
+}
+
+int clear_enqueue(sr_ctx *ctx, const ClearList &cl)
+{
+    int64_t mx = 0;
+    for (int k = 0; k < 4; ++k)
+        if (cl.p[k] && cl.n[k] > mx)
+            mx = cl.n[k];
+    if (mx <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_clear, dim3(blocks_for(mx, kBlock)), dim3(kBlock), 0, ctx->stream, cl);
+    return sr_check_launch(ctx, "k_clear");
 }
 
 void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
@@ -474,6 +538,7 @@ void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
     s.large_list = b.take<int>(nn / (kLargeCell + 1) + 1);
     s.large_count = b.take<int>(1);
     s.mass_mixed = b.take<int>((size_t)(nb > 0 ? nb : 1));
+    s.scan_flag = b.take<int>(1);
 }
 
 // Enqueue the whole binning pass.  sorted and chunk_count may be NULL (then
@@ -482,20 +547,27 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
                 float4 *sorted, int *chunk_count)
 {
     int rc;
-    if ((rc = fill_enqueue(ctx, s.count, 0, B.ctot)))
-        return rc;
-    if ((rc = fill_enqueue(ctx, s.large_count, 0, 1)))
-        return rc;
-    if ((rc = fill_enqueue(ctx, s.mass_mixed, 0, B.nb)))
-        return rc;
+    {
+        ClearList cl{};
+        cl.p[0] = s.count;
+        cl.n[0] = B.ctot;
+        cl.p[1] = s.large_count;
+        cl.n[1] = 1;
+        cl.p[2] = s.mass_mixed;
+        cl.n[2] = B.nb;
+        cl.p[3] = s.scan_flag;
+        cl.n[3] = 1;
+        if ((rc = clear_enqueue(ctx, cl)))
+            return rc;
+    }
     const int n = B.ntot;
     if (n > 0) {
-        hipLaunchKernelGGL(k_cellid, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
-                           B, s.cid, s.slot, s.count, ctx->status);
+        hipLaunchKernelGGL(k_cellid, dim3(blocks_for(n, kCellidBlock)), dim3(kBlock), 0,
+                           ctx->stream, B, s.cid, s.slot, s.count, ctx->status);
         if ((rc = sr_check_launch(ctx, "k_cellid")))
             return rc;
     }
-    if ((rc = scan_enqueue(ctx, s.count, B.ctot, s.scan_part, offsets)))
+    if ((rc = scan_enqueue(ctx, s.count, B.ctot, s.scan_part, offsets, s.scan_flag)))
         return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
@@ -503,17 +575,25 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
         if ((rc = sr_check_launch(ctx, "k_scatter")))
             return rc;
     }
+    // the arrival ranks are no longer needed: reuse them as the inverse
+    int *inv = sorted ? s.slot : nullptr;
     hipLaunchKernelGGL(k_segsort, dim3(blocks_for(B.ctot, kBlock / 64)), dim3(kBlock), 0,
-                       ctx->stream, B, offsets, perm, s.large_list, s.large_count, sorted,
-                       chunk_count, s.mass_mixed);
+                       ctx->stream, B, offsets, perm, s.large_list, s.large_count, inv,
+                       chunk_count);
     if ((rc = sr_check_launch(ctx, "k_segsort")))
         return rc;
     if (n > kLargeCell) {
         int max_large = n / (kLargeCell + 1) + 1;
         int grid = max_large < 2048 ? max_large : 2048;
         hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kBlock), 0, ctx->stream, B, offsets,
-                           perm, s.tmp, s.large_list, s.large_count, sorted, s.mass_mixed);
+                           perm, s.tmp, s.large_list, s.large_count, inv);
         if ((rc = sr_check_launch(ctx, "k_segsort_large")))
+            return rc;
+    }
+    if (sorted && n > 0) {
+        hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
+                           B, inv, sorted, s.mass_mixed);
+        if ((rc = sr_check_launch(ctx, "k_gather")))
             return rc;
     }
     return SR_OK;

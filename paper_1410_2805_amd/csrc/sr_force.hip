@@ -575,13 +575,22 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const int4 *__restrict__ it
     }
 }
 
-// FP64 sum_i m_i a_i per box: fixed per-thread ranges, fixed tree order.
+// FP64 sum_i m_i a_i per box.  Box b is cut into R_b = min(kRedBlocks,
+// ceil(n_b / 4096)) contiguous chunks, one per block; within a block each
+// thread sums a fixed strided subset and the block adds them in a fixed tree
+// order.  Blocks past R_b contribute exact zeros, so a box's sum depends on
+// that box alone (bitwise the same alone and in a batch).
 __global__ __launch_bounds__(256) void k_momentum_partial(Batch B, double *__restrict__ part)
 {
     __shared__ double sh[3][256];
     const BoxDesc &d = box_at(B, blockIdx.y);
+    int R = (d.n + 4095) / 4096;
+    R = R < 1 ? 1 : (R > kRedBlocks ? kRedBlocks : R);
+    const int chunk = (d.n + R - 1) / R;
+    const int lo = blockIdx.x * chunk;
+    const int hi = (int)blockIdx.x < R ? (lo + chunk < d.n ? lo + chunk : d.n) : lo;
     double s[3] = {0.0, 0.0, 0.0};
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < d.n; i += kRedBlocks * 256) {
+    for (int i = lo + threadIdx.x; i < hi; i += 256) {
         const double mi = (double)d.m[i];
         s[0] += mi * (double)d.ax[i];
         s[1] += mi * (double)d.ay[i];
@@ -601,14 +610,26 @@ __global__ __launch_bounds__(256) void k_momentum_partial(Batch B, double *__res
             part[(blockIdx.y * kRedBlocks + blockIdx.x) * 3 + k] = sh[k][0];
 }
 
-__global__ void k_momentum_final(const double *__restrict__ part, double *__restrict__ out)
+// One block per box: the kRedBlocks partials added in a fixed tree order.
+__global__ __launch_bounds__(256) void k_momentum_final(const double *__restrict__ part,
+                                                        double *__restrict__ out)
 {
-    if (threadIdx.x < 3) {
-        double s = 0.0;
-        for (int b = 0; b < kRedBlocks; ++b)
-            s += part[(blockIdx.x * kRedBlocks + b) * 3 + threadIdx.x];
-        out[3 * blockIdx.x + threadIdx.x] = s;
+    __shared__ double sh[3][256];
+    for (int k = 0; k < 3; ++k) {
+        double v = 0.0;
+        for (int r = threadIdx.x; r < kRedBlocks; r += 256)
+            v += part[(blockIdx.x * kRedBlocks + r) * 3 + k];
+        sh[k][threadIdx.x] = v;
     }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < 3; ++k)
+                sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3)
+        out[3 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 unsigned grid_for_items(int64_t ub)
@@ -716,7 +737,7 @@ ForceParams make_params(float r_max, float eps, const float *poly)
 static int items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, int order)
 {
     int rc;
-    if ((rc = scan_enqueue(ctx, s.chunk_count, B.ctot, s.scan_part2, s.item_off)))
+    if ((rc = scan_enqueue(ctx, s.chunk_count, B.ctot, s.scan_part2, s.item_off, s.bin.scan_flag)))
         return rc;
     hipLaunchKernelGGL(k_items, dim3((B.ctot + 255) / 256), dim3(256), 0, ctx->stream, B,
                        s.offsets, s.item_off, s.items, s.item_cost);
@@ -727,7 +748,7 @@ static int items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, int
         const int *n_items = s.item_off + B.ctot;
         hipLaunchKernelGGL(k_lpt_hist, dim3(nblk), dim3(256), 0, ctx->stream, s.item_cost,
                            n_items, nblk, s.lpt_hist);
-        if ((rc = scan_enqueue(ctx, s.lpt_hist, 32 * nblk, s.lpt_part, s.lpt_off)))
+        if ((rc = scan_enqueue(ctx, s.lpt_hist, 32 * nblk, s.lpt_part, s.lpt_off, s.bin.scan_flag)))
             return rc;
         hipLaunchKernelGGL(k_lpt_scatter, dim3(nblk), dim3(256), 0, ctx->stream, s.items,
                            s.item_cost, n_items, nblk, s.lpt_off, s.items_lpt);
@@ -775,7 +796,7 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
     if (mom) {
         hipLaunchKernelGGL(k_momentum_partial, dim3(kRedBlocks, B.nb), dim3(256), 0, ctx->stream,
                            B, s.mom_part);
-        hipLaunchKernelGGL(k_momentum_final, dim3(B.nb), dim3(64), 0, ctx->stream, s.mom_part,
+        hipLaunchKernelGGL(k_momentum_final, dim3(B.nb), dim3(256), 0, ctx->stream, s.mom_part,
                            mom);
         if ((rc = sr_check_launch(ctx, "k_momentum")))
             return rc;

@@ -139,6 +139,13 @@ struct BinScratch {
     int *large_list;  // [max_large] cells too big for one wavefront's LDS
     int *large_count; // [1]
     int *mass_mixed;  // [nb] box b: 1 if any of its masses differs from its first
+    int *scan_flag;   // [1] last-block counter of the scans (kept at 0)
+};
+
+// Up to four int buffers zeroed by one kernel launch.
+struct ClearList {
+    int *p[4];
+    int64_t n[4];
 };
 
 // Everything a force pass needs beyond binning.
@@ -160,7 +167,7 @@ struct ForceScratch {
     double *mom_part; // [nb * kRedBlocks * 3]
 };
 
-constexpr int kRedBlocks = 64;     // FP64 reduction blocks per box
+constexpr int kRedBlocks = 512;    // FP64 reduction blocks per box (at most)
 constexpr int kLargeCell = 1024;   // cells above this are sorted by a whole block
 constexpr int kChunk = 64;         // maximum targets per force work item
 constexpr int kMaxSplit = 16;      // at most 16 lane groups share one target
@@ -180,8 +187,9 @@ void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s);
 int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, int *perm,
                 float4 *sorted, int *chunk_count);
 void scan_layout(Bump &b, int m, int **part);
-int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out);
+int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out, int *flag);
 int fill_enqueue(sr_ctx *ctx, int *p, int value, int64_t count);
+int clear_enqueue(sr_ctx *ctx, const ClearList &cl);
 
 // Force pass (sr_force.hip)
 int64_t item_bound(int64_t ntot, int64_t ctot);
