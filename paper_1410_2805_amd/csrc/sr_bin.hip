@@ -323,25 +323,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(Batch B, const int *__restric
         atomicOr(&mass_mixed[box], 1);
 }
 
-// One wavefront per cell.
-__global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restrict__ offsets,
-                                                    int *__restrict__ perm,
-                                                    int *__restrict__ large_list,
-                                                    int *__restrict__ large_count,
-                                                    int *__restrict__ inv,
-                                                    int *__restrict__ chunk_count)
+constexpr int kSegGroup = 4;  // consecutive cells per wavefront
+
+// Sorts one cell's slots [b, b + len) by one wavefront (len <= kLargeCell;
+// larger cells are queued for k_segsort_large).
+__device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int *sb,
+                          int *__restrict__ large_list, int *__restrict__ large_count,
+                          int *__restrict__ inv, int lane)
 {
-    __shared__ int buf[kBlock / 64][kLargeCell];
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int cell = blockIdx.x * (kBlock / 64) + wid;
-    if (cell >= B.ctot)
-        return;
-    // one cell per wavefront: its bounds are wavefront-uniform
-    const int b = __builtin_amdgcn_readfirstlane(offsets[cell]);
-    const int len = __builtin_amdgcn_readfirstlane(offsets[cell + 1]) - b;
-    if (chunk_count && lane == 0)
-        chunk_count[cell] = chunks_for(len);
     if (len <= 32) {
         // small cell: each index's rank is the number of smaller ones
         const int v = lane < len ? perm[b + lane] : INT_MAX;
@@ -365,7 +354,6 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
         int P = 128;
         while (P < len)
             P <<= 1;
-        int *sb = buf[wid];
         for (int t = lane; t < P; t += 64)
             sb[t] = t < len ? perm[b + t] : INT_MAX;
         wave_sync();
@@ -376,10 +364,68 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
             if (inv)
                 inv[v] = b + t;
         }
+        wave_sync();
     } else if (lane == 0) {
         int k = atomicAdd(large_count, 1);
         large_list[k] = cell;
     }
+}
+
+// One wavefront per group of kSegGroup consecutive cells.  When the group
+// holds at most 64 particles, each lane takes one slot and ranks its index
+// among the smaller indices of the same cell (one pass for the whole group);
+// otherwise the cells are sorted one after the other.
+__global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restrict__ offsets,
+                                                    int *__restrict__ perm,
+                                                    int *__restrict__ large_list,
+                                                    int *__restrict__ large_count,
+                                                    int *__restrict__ inv,
+                                                    int *__restrict__ chunk_count)
+{
+    __shared__ int buf[kBlock / 64][kLargeCell];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int c0 = (blockIdx.x * (kBlock / 64) + wid) * kSegGroup;
+    if (c0 >= B.ctot)
+        return;
+    const int nc = B.ctot - c0 < kSegGroup ? B.ctot - c0 : kSegGroup;
+    int bounds[kSegGroup + 1];
+#pragma unroll
+    for (int k = 0; k <= kSegGroup; ++k)
+        bounds[k] = __builtin_amdgcn_readfirstlane(offsets[c0 + (k < nc ? k : nc)]);
+    if (chunk_count && lane < nc)
+        chunk_count[c0 + lane] = chunks_for(offsets[c0 + lane + 1] - offsets[c0 + lane]);
+    const int b = bounds[0];
+    const int total = bounds[kSegGroup] - b;
+    if (total <= 64) {
+        // my slot, my cell (by the group's inner bounds), my index
+        const int slot = b + lane;
+        int mycell = 0;
+#pragma unroll
+        for (int k = 1; k < kSegGroup; ++k)
+            mycell += slot >= bounds[k] ? 1 : 0;
+        const int v = lane < total ? perm[slot] : INT_MAX;
+        const int key_cell = lane < total ? mycell : kSegGroup;
+        int rank = 0;
+        for (int k = 0; k < total; ++k) {
+            const int u = __builtin_amdgcn_readlane(v, k);
+            const int uc = __builtin_amdgcn_readlane(key_cell, k);
+            rank += (uc == key_cell && u < v) ? 1 : 0;
+        }
+        if (lane < total) {
+            int cb = bounds[0];
+#pragma unroll
+            for (int k = 1; k < kSegGroup; ++k)
+                cb = mycell >= k ? bounds[k] : cb;
+            perm[cb + rank] = v;
+            if (inv)
+                inv[v] = cb + rank;
+        }
+        return;
+    }
+    for (int k = 0; k < nc; ++k)
+        sort_cell(c0 + k, bounds[k], bounds[k + 1] - bounds[k], perm, buf[wid], large_list,
+                  large_count, inv, lane);
 }
 
 // Block-level sort of one large cell: LDS-sorted runs of kLargeCell, then
@@ -577,7 +623,7 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
     }
     // the arrival ranks are no longer needed: reuse them as the inverse
     int *inv = sorted ? s.slot : nullptr;
-    hipLaunchKernelGGL(k_segsort, dim3(blocks_for(B.ctot, kBlock / 64)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(k_segsort, dim3(blocks_for(B.ctot, kBlock / 64 * kSegGroup)), dim3(kBlock), 0,
                        ctx->stream, B, offsets, perm, s.large_list, s.large_count, inv,
                        chunk_count);
     if ((rc = sr_check_launch(ctx, "k_segsort")))
