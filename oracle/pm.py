@@ -22,7 +22,9 @@ ksk_step composes these with the short-range stream-kick-stream map of the
 C oracle into the subcycled step of Eq. (tstep) (Sec. 2.5).
 
 Readings (also listed in the design notes): the filter's sinc factor is
-taken per axis (separable, the form of a TSC-like window), k_i = 2 pi n_i / L
+taken per axis (separable, the form of a TSC-like window), sigma is measured
+in grid spacings (the matching scale and the fit of Eq. (fitform) are in grid
+units), k_i = 2 pi n_i / L
 with n_i the signed integer frequency, and the derivative formula is read
 with the exponent e^{i 2 pi j x / L} (the printed formula drops the i).
 """
@@ -56,11 +58,12 @@ def green6(ng: int, L: float) -> np.ndarray:
 
 
 def sinc_gauss(ng: int, L: float, sigma: float = 0.8, ns: int = 3) -> np.ndarray:
-    """S(k) of Eq. (filter), sinc factor per axis."""
+    """S(k) of Eq. (filter), sinc factor per axis; sigma in grid spacings."""
     d = L / ng
     kx, ky, kz = _freqs(ng, L)
     k2 = kx * kx + ky * ky + kz * kz
-    out = np.exp(-k2 * sigma * sigma / 4.0)
+    sd = sigma * d
+    out = np.exp(-k2 * sd * sd / 4.0)
     for kc in (kx, ky, kz):
         x = kc * d / 2.0
         with np.errstate(invalid="ignore", divide="ignore"):

@@ -16,7 +16,8 @@ SRC = pm.__file__
 MUTANTS = [
     ("no filter", "out = out * sc ** ns", "out = out * 1.0"),
     ("filter power", "out = out * sc ** ns", "out = out * sc ** (ns - 1)"),
-    ("gaussian width", "np.exp(-k2 * sigma * sigma / 4.0)", "np.exp(-k2 * sigma * sigma / 2.0)"),
+    ("gaussian width", "np.exp(-k2 * sd * sd / 4.0)", "np.exp(-k2 * sd * sd / 2.0)"),
+    ("sigma in length units", "sd = sigma * d", "sd = sigma"),
     ("G6 second weight", "(5.0 / 64.0) * np.cos(2 * kc * d)", "(5.0 / 32.0) * np.cos(2 * kc * d)"),
     ("G6 constant", "s = s - 2835.0 / 1024.0", "s = s - 2836.0 / 1024.0"),
     ("G6 normalisation", "(45.0 / 128.0) * d * d / s", "(45.0 / 64.0) * d * d / s"),
@@ -36,6 +37,7 @@ PINS = [
     P.test_green6_sixth_order_along_an_axis,
     P.test_super_lanczos_fourth_order,
     P.test_filter_limits,
+    P.test_grid_unit_scaling,
     P.test_cic_identities,
     P.test_newton_third_law_and_no_self_force,
     lambda: [P.test_test_pair_reproduces_fitform(r) for r in (1.0, 3.0)],

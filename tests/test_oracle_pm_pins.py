@@ -77,6 +77,18 @@ def test_filter_limits():
     assert s[0, 0, 5] == pytest.approx(s[5, 0, 0], rel=1e-14)
 
 
+def test_grid_unit_scaling():
+    """Lengths in grid spacings: doubling L and every position at fixed N_g
+    (and fixed masses) divides every acceleration by exactly 4."""
+    ng = 16
+    rng = np.random.default_rng(5)
+    pos = rng.random((40, 3)) * 20.0
+    m = rng.uniform(0.5, 2.0, 40)
+    a1 = pm.pm_accel(pos, m, ng, 20.0)
+    a2 = pm.pm_accel(2.0 * pos, m, ng, 40.0)
+    assert np.allclose(a2 * 4.0, a1, rtol=1e-10, atol=1e-13 * np.abs(a1).max())
+
+
 def test_cic_identities():
     ng, L = 12, 30.0
     d = L / ng
