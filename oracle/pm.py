@@ -121,16 +121,19 @@ def cic_interp(grid: np.ndarray, pos: np.ndarray, ng: int, L: float) -> np.ndarr
     return out
 
 
-def pm_accel(pos, m, ng: int, L: float, sigma: float = 0.8, ns: int = 3) -> np.ndarray:
-    """(n, 3) long-range accelerations of all particles (float64)."""
+def pm_accel(pos, m, ng: int, L: float, sigma: float = 0.8, ns: int = 3,
+             targets=None) -> np.ndarray:
+    """(n, 3) long-range accelerations (float64) of all particles, or of the
+    particles listed in targets (every particle still sources the field)."""
     pos = np.asarray(pos, dtype=np.float64)
     m = np.asarray(m, dtype=np.float64)
     rho_k = np.fft.rfftn(cic_deposit(pos, m, ng, L))
     phi_k = 4.0 * np.pi * green6(ng, L) * sinc_gauss(ng, L, sigma, ns) * rho_k
-    acc = np.zeros_like(pos)
+    at = pos if targets is None else pos[np.asarray(targets)]
+    acc = np.zeros_like(at)
     for ax in range(3):
         a_grid = np.fft.irfftn(-sl_derivative(ng, L, ax) * phi_k, s=(ng, ng, ng), axes=(0, 1, 2))
-        acc[:, ax] = cic_interp(a_grid, pos, ng, L)
+        acc[:, ax] = cic_interp(a_grid, at, ng, L)
     return acc
 
 

@@ -289,6 +289,9 @@ extern "C" int sr_sync(sr_ctx *ctx)
     if (st != 0) {
         int zero = 0;
         (void)hipMemcpy(ctx->status, &zero, sizeof(int), hipMemcpyHostToDevice);
+        if (st & 2)
+            return sr_fail(ctx, SR_ERANGE, "a mass was negative or not finite, or a PM position "
+                                           "was not finite");
         return sr_fail(ctx, SR_ERANGE, "a coordinate was outside [0, L) or NaN");
     }
     return SR_OK;

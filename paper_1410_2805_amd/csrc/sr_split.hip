@@ -149,6 +149,47 @@ __global__ __launch_bounds__(kBlock) void k_slot_update(const SlotState *__restr
     S.cell3[li] = pack3(c);
 }
 
+// One box of split state: kick v += a * kick (when a is given), then stream
+// o += v * stream in FP64 with re-homing (stream == 0: kick only).  The
+// arithmetic of each map is that of k_slot_update.
+__global__ __launch_bounds__(kBlock) void k_kick_stream(SplitGeom sg, int n, int *__restrict__ cell3,
+                                                        float *__restrict__ ox,
+                                                        float *__restrict__ oy,
+                                                        float *__restrict__ oz,
+                                                        float *__restrict__ vx,
+                                                        float *__restrict__ vy,
+                                                        float *__restrict__ vz,
+                                                        const float *__restrict__ ax,
+                                                        const float *__restrict__ ay,
+                                                        const float *__restrict__ az, float kick,
+                                                        double stream)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    float v[3] = {vx[i], vy[i], vz[i]};
+    if (ax) {
+        v[0] = fmaf(ax[i], kick, v[0]);
+        v[1] = fmaf(ay[i], kick, v[1]);
+        v[2] = fmaf(az[i], kick, v[2]);
+        vx[i] = v[0];
+        vy[i] = v[1];
+        vz[i] = v[2];
+    }
+    if (stream == 0.0)
+        return;
+    int c[3];
+    unpack3(cell3[i], c);
+    float *o[3] = {ox, oy, oz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double off = (double)o[k][i] + (double)v[k] * stream;
+        rehome(off, c[k], sg.h[k], sg.nc[k]);
+        o[k][i] = (float)off;
+    }
+    cell3[i] = pack3(c);
+}
+
 }  // namespace
 
 int split_geom(sr_ctx *ctx, const sr_box *box, double cell, SplitGeom *sg)
@@ -236,4 +277,16 @@ extern "C" int sr_split_to_f64(sr_ctx *ctx, const int32_t *cell3, const float *o
     if (hipSetDevice(ctx->device) != hipSuccess)
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
     return split_to_f64_enqueue(ctx, cell3, ox, oy, oz, (int)n, sg, x, y, z);
+}
+
+int kick_stream_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
+                        float *oz, float *vx, float *vy, float *vz, const float *ax,
+                        const float *ay, const float *az, float kick, double stream)
+{
+    if (n <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_kick_stream, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       ctx->stream, sg, n, cell3, ox, oy, oz, vx, vy, vz, ax, ay, az, kick,
+                       stream);
+    return sr_check_launch(ctx, "k_kick_stream");
 }

@@ -1,0 +1,73 @@
+// The full step of Eq. (tstep) (Sec. 2.5): long-range half kicks around
+// n_sub short-range stream-kick-stream subcycles, on resident split state.
+#include <cmath>
+
+#include "sr_internal.h"
+#include "sr_pm.h"
+#include "sr_split.h"
+
+// sr_pm.hip
+int pm_force_split_enqueue(sr_pm *pm, const int32_t *cell3, const float *ox, const float *oy,
+                           const float *oz, const float *mass, int n, const double h[3],
+                           float *ax, float *ay, float *az);
+sr_ctx *pm_context(const sr_pm *pm);
+double pm_len(const sr_pm *pm);
+
+extern "C" int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, float *oy,
+                           float *oz, float *vx, float *vy, float *vz, const float *mass,
+                           int64_t n, const sr_box *box, const sr_step_params *p, float *lr_ax,
+                           float *lr_ay, float *lr_az, int32_t lr_valid, float *sr_ax,
+                           float *sr_ay, float *sr_az)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    if (!pm || pm_context(pm) != ctx)
+        return sr_fail(ctx, SR_EINVAL, "the PM solver must belong to this context");
+    if (!box || !p)
+        return sr_fail(ctx, SR_EINVAL, "NULL box or parameters");
+    const double len = pm_len(pm);
+    if (!box->periodic || box->len[0] != len || box->len[1] != len || box->len[2] != len)
+        return sr_fail(ctx, SR_EINVAL, "the box must be the PM solver's periodic cube");
+    if (n < 0 || n > INT_MAX)
+        return sr_fail(ctx, SR_EINVAL, "n out of range");
+    if (n > 0 && (!cell3 || !ox || !oy || !oz || !vx || !vy || !vz || !mass || !lr_ax ||
+                  !lr_ay || !lr_az || !sr_ax || !sr_ay || !sr_az))
+        return sr_fail(ctx, SR_EINVAL, "NULL pointer with n > 0");
+    if (p->n_sub < 1 || !std::isfinite(p->dt))
+        return sr_fail(ctx, SR_EINVAL, "n_sub must be >= 1 and dt finite");
+    SplitGeom sg;
+    int rc = split_geom(ctx, box, p->cell, &sg);
+    if (rc)
+        return rc;
+    if ((rc = check_force_params(ctx, p->r_max, p->eps, p->poly)))
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    const int ni = (int)n;
+    if (!lr_valid &&
+        (rc = pm_force_split_enqueue(pm, cell3, ox, oy, oz, mass, ni, sg.h, lr_ax, lr_ay, lr_az)))
+        return rc;
+    const double tau = (double)p->dt / p->n_sub;
+    const double half_tau = 0.5 * tau;
+    const float half_dt = (float)(0.5 * (double)p->dt);
+    // long-range half kick fused with the first subcycle's first stream
+    if ((rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, lr_ax, lr_ay, lr_az,
+                                  half_dt, half_tau)))
+        return rc;
+    for (int c = 0; c < p->n_sub; ++c) {
+        if (c > 0 && (rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, nullptr,
+                                               nullptr, nullptr, 0.f, half_tau)))
+            return rc;
+        if ((rc = sr_force_split(ctx, cell3, ox, oy, oz, mass, n, box, p->cell, p->r_max, p->eps,
+                                 p->poly, sr_ax, sr_ay, sr_az, nullptr)))
+            return rc;
+        if ((rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, sr_ax, sr_ay,
+                                      sr_az, (float)tau, half_tau)))
+            return rc;
+    }
+    if ((rc = pm_force_split_enqueue(pm, cell3, ox, oy, oz, mass, ni, sg.h, lr_ax, lr_ay, lr_az)))
+        return rc;
+    return kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, lr_ax, lr_ay, lr_az,
+                               half_dt, 0.0);
+}

@@ -87,6 +87,22 @@ class ServerInfo(ctypes.Structure):
                 ("scratch_bytes_capacity", ctypes.c_size_t), ("ticks", ctypes.c_int64)]
 
 
+class StepParams(ctypes.Structure):
+    """sr_step_params: one full step of Eq. (tstep)."""
+
+    _fields_ = [("r_max", ctypes.c_float), ("eps", ctypes.c_float), ("poly", ctypes.c_float * 6),
+                ("cell", ctypes.c_double), ("dt", ctypes.c_float), ("n_sub", ctypes.c_int32)]
+
+    @staticmethod
+    def make(r_max, eps, poly, cell, dt, n_sub) -> "StepParams":
+        p = StepParams()
+        p.r_max, p.eps, p.cell, p.dt, p.n_sub = float(r_max), float(eps), float(cell), float(dt), \
+            int(n_sub)
+        for k in range(6):
+            p.poly[k] = float(poly[k])
+        return p
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsr.so not built at %s (run __graft_entry__.build())" % LIB_PATH)
@@ -134,6 +150,15 @@ def _load():
         "sr_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "sr_timing_collect": (ctypes.c_int, [P, ctypes.POINTER(f64), ctypes.POINTER(f64),
                                              ctypes.POINTER(i64)]),
+        "sr_pm_create": (ctypes.c_int, [P, i32, f64, f32, i32, ctypes.POINTER(P)]),
+        "sr_pm_destroy": (ctypes.c_int, [P]),
+        "sr_pm_bytes": (ctypes.c_int, [i32, ctypes.POINTER(sz)]),
+        "sr_pm_deposit": (ctypes.c_int, [P, P, P, P, P, i64, P]),
+        "sr_pm_fft": (ctypes.c_int, [P, P, i32]),
+        "sr_pm_force": (ctypes.c_int, [P, P, P, P, P, i64, P, P, P]),
+        "sr_pm_force_split": (ctypes.c_int, [P, P, P, P, P, P, i64, f64, P, P, P]),
+        "sr_ksk_step": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, i64, BP,
+                                       ctypes.POINTER(StepParams), P, P, P, i32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -153,7 +178,9 @@ def exported_symbols() -> list[str]:
             "sr_plan_create", "sr_plan_set_tuning", "sr_plan_get_tuning", "sr_plan_run",
             "sr_plan_capture", "sr_plan_launch", "sr_plan_autotune", "sr_plan_destroy",
             "sr_server_create", "sr_server_submit", "sr_server_tick", "sr_server_poll",
-            "sr_server_cancel", "sr_server_info_get", "sr_server_destroy"]
+            "sr_server_cancel", "sr_server_info_get", "sr_server_destroy",
+            "sr_pm_create", "sr_pm_destroy", "sr_pm_bytes", "sr_pm_deposit", "sr_pm_fft",
+            "sr_pm_force", "sr_pm_force_split", "sr_ksk_step"]
 
 
 def _ptr(t):
@@ -538,3 +565,102 @@ def pinned_empty(shape, dtype):
 
 def pinned_release(a) -> None:
     _PINNED.pop(a.ctypes.data, None)
+
+
+# ---- long-range PM force and the full step (include/sr_pm.h) -------------
+
+def sr_pm_bytes(ng: int) -> int:
+    out = ctypes.c_size_t()
+    rc = lib.sr_pm_bytes(int(ng), ctypes.byref(out))
+    if rc:
+        raise SRError(rc, "bad grid size")
+    return int(out.value)
+
+
+class PM:
+    """sr_pm: the long-range solver of one periodic cube (ng^3 grid)."""
+
+    def __init__(self, ctx: Context, ng: int, L: float, sigma: float = 0.8, ns: int = 3):
+        self.ctx, self.ng, self.L = ctx, int(ng), float(L)
+        h = ctypes.c_void_p()
+        ctx._bind_stream()
+        ctx._check(lib.sr_pm_create(ctx._h, self.ng, self.L, float(sigma), int(ns),
+                                    ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sr_pm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out3(self, n, dev, out):
+        if out is None:
+            out = tuple(torch.empty(max(n, 1), dtype=torch.float32, device=dev)[:n]
+                        for _ in range(3))
+        return out
+
+    def deposit(self, x, y, z, m, rho=None):
+        """CIC density (ng, ng, ng) float32 (mass per cell volume)."""
+        n = int(x.shape[0])
+        g = self.ng
+        if rho is None:
+            rho = torch.empty((g, g, g), dtype=torch.float32, device=x.device)
+        if not (rho.is_cuda and rho.dtype == torch.float32 and rho.is_contiguous()
+                and rho.numel() == g ** 3):
+            raise ValueError("rho must be a contiguous float32 CUDA tensor of ng^3 values")
+        self.ctx._bind_stream()
+        self.ctx._check(lib.sr_pm_deposit(self._h, _f32(x, n, "x"), _f32(y, n, "y"),
+                                          _f32(z, n, "z"), _f32(m, n, "mass"), n, _ptr(rho)))
+        return rho
+
+    def fft(self, data, inverse: bool = False):
+        """In-place unnormalised 3-D DFT of a complex64 (ng, ng, ng) tensor."""
+        g = self.ng
+        if not (isinstance(data, torch.Tensor) and data.is_cuda and data.dtype == torch.complex64
+                and data.is_contiguous() and data.numel() == g ** 3):
+            raise ValueError("data must be a contiguous complex64 CUDA tensor of ng^3 values")
+        self.ctx._bind_stream()
+        self.ctx._check(lib.sr_pm_fft(self._h, _ptr(data), 1 if inverse else 0))
+        return data
+
+    def force(self, x, y, z, m, out=None):
+        n = int(x.shape[0])
+        ax, ay, az = self._out3(n, x.device, out)
+        self.ctx._bind_stream()
+        self.ctx._check(lib.sr_pm_force(self._h, _f32(x, n, "x"), _f32(y, n, "y"),
+                                        _f32(z, n, "z"), _f32(m, n, "mass"), n,
+                                        _f32(ax, n, "ax"), _f32(ay, n, "ay"), _f32(az, n, "az")))
+        return ax, ay, az
+
+    def force_split(self, cell3, ox, oy, oz, m, cell: float, out=None):
+        n = int(cell3.shape[0])
+        ax, ay, az = self._out3(n, cell3.device, out)
+        self.ctx._bind_stream()
+        self.ctx._check(lib.sr_pm_force_split(
+            self._h, _typed(cell3, n, torch.int32, "cell3"), _f32(ox, n, "ox"), _f32(oy, n, "oy"),
+            _f32(oz, n, "oz"), _f32(m, n, "mass"), n, float(cell), _f32(ax, n, "ax"),
+            _f32(ay, n, "ay"), _f32(az, n, "az")))
+        return ax, ay, az
+
+
+def sr_ksk_step(ctx: Context, pm: PM, state: dict, box: Box, params: StepParams, lr, lr_valid,
+                sr_out):
+    """One full step on split state {cell3, ox, oy, oz, vx, vy, vz, m} (updated
+    in place); lr = (ax, ay, az) PM acceleration (in/out), sr_out receives the
+    last subcycle's short-range acceleration."""
+    n = int(state["cell3"].shape[0])
+    ctx._bind_stream()
+    ctx._check(lib.sr_ksk_step(
+        ctx._h, pm._h, _typed(state["cell3"], n, torch.int32, "cell3"),
+        _f32(state["ox"], n, "ox"), _f32(state["oy"], n, "oy"), _f32(state["oz"], n, "oz"),
+        _f32(state["vx"], n, "vx"), _f32(state["vy"], n, "vy"), _f32(state["vz"], n, "vz"),
+        _f32(state["m"], n, "mass"), n, ctypes.byref(box), ctypes.byref(params),
+        _f32(lr[0], n, "lr_ax"), _f32(lr[1], n, "lr_ay"), _f32(lr[2], n, "lr_az"),
+        1 if lr_valid else 0, _f32(sr_out[0], n, "sr_ax"), _f32(sr_out[1], n, "sr_ay"),
+        _f32(sr_out[2], n, "sr_az")))

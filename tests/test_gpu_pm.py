@@ -1,0 +1,329 @@
+"""Long-range PM force (Sec. 2.3) and the full step of Eq. (tstep): the HIP
+path against the FP64 PM oracle.
+
+Tolerances (float32 path against FP64):
+  FFT      relative RMS error <= 5e-7 log2(N) (N = ng^3 points): float32
+           Stockham butterflies add about one rounding per radix-4 stage.
+  deposit  every grid value within 2^-22 of the oracle's (fixed-point sums,
+           one final rounding to float32).
+  force    relRMS <= 5e-6 and per particle |da| <= 1e-5 rms|a| + 1e-4 |a|:
+           four float32 FFT passes of ~1e-6 relative RMS each (the bound of
+           the FFT line above at N = 2^21), table factors and CIC weights
+           rounded to float32; measured errors are 1e-7 .. 5e-7 relRMS.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import pm as PMO
+from paper_1410_2805_amd import gridfit
+from paper_1410_2805_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FORCE_RMS_TOL = 5e-6
+
+
+@pytest.fixture(scope="module")
+def sr():
+    from paper_1410_2805_amd import sr as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(sr):
+    c = sr.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dtype)
+
+
+def _np(*ts):
+    return torch.stack(ts, 1).double().cpu().numpy()
+
+
+def check_pm_accel(a_gpu, a_ref, label=""):
+    err = np.linalg.norm(a_gpu - a_ref, axis=1)
+    nref = np.linalg.norm(a_ref, axis=1)
+    rms = math.sqrt(float((nref ** 2).mean())) if nref.size else 0.0
+    rel_rms = math.sqrt(float((err ** 2).sum()) / max(float((nref ** 2).sum()), 1e-300))
+    bound = 1e-5 * rms + 1e-4 * nref
+    bad = np.nonzero(err > bound)[0]
+    print("%s: relRMS %.3e max err/rms %.3e" % (label, rel_rms, err.max() / max(rms, 1e-300)))
+    assert rel_rms <= FORCE_RMS_TOL, "%s relRMS %.3e" % (label, rel_rms)
+    assert bad.size == 0, "%s per-particle bound at %s: %s > %s" % (label, bad[:4], err[bad[:4]],
+                                                                  bound[bad[:4]])
+    return rel_rms
+
+
+@pytest.mark.parametrize("ng", [8, 16, 32, 64, 128])
+def test_fft_matches_library(sr, ctx, ng):
+    pmh = sr.PM(ctx, ng, float(ng))
+    try:
+        rng = np.random.default_rng(ng)
+        x = (rng.normal(size=(ng,) * 3) + 1j * rng.normal(size=(ng,) * 3)).astype(np.complex64)
+        d = torch.from_numpy(x).to("cuda:0")
+        pmh.fft(d)
+        ctx.sync()
+        ref = np.fft.fftn(x.astype(np.complex128))
+        got = d.cpu().numpy().astype(np.complex128)
+        tol = 5e-7 * math.log2(ng ** 3)
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert rel <= tol, (ng, rel)
+        pmh.fft(d, inverse=True)
+        ctx.sync()
+        back = d.cpu().numpy().astype(np.complex128) / ng ** 3
+        rel_b = np.linalg.norm(back - x) / np.linalg.norm(x)
+        assert rel_b <= 2 * tol, (ng, rel_b)
+        # inverse alone against the library
+        d2 = torch.from_numpy(x).to("cuda:0")
+        pmh.fft(d2, inverse=True)
+        ctx.sync()
+        ref_i = np.fft.ifftn(x.astype(np.complex128)) * ng ** 3
+        rel_i = np.linalg.norm(d2.cpu().numpy() - ref_i) / np.linalg.norm(ref_i)
+        assert rel_i <= tol, (ng, rel_i)
+    finally:
+        pmh.close()
+
+
+def _deposit_check(sr, ctx, pos32, m, ng, L):
+    pmh = sr.PM(ctx, ng, L)
+    try:
+        t = [_dev(pos32[:, d]) for d in range(3)]
+        tm = _dev(m)
+        rho = pmh.deposit(*t, tm)
+        ctx.sync()
+        got = rho.double().cpu().numpy()
+        ref = PMO.cic_deposit(pos32.astype(np.float64), m.astype(np.float64), ng, L)
+        scale = max(float(np.abs(ref).max()), 1e-300)
+        assert np.all(np.abs(got - ref) <= 2.0 ** -22 * np.abs(ref) + 1e-12 * scale), ng
+        return rho, t, tm, pmh
+    except Exception:
+        pmh.close()
+        raise
+
+
+@pytest.mark.parametrize("ng,n,L", [(8, 1, 8.0), (16, 5000, 20.0), (32, 40000, 32.0),
+                                    (64, 100000, 50.0)])
+def test_deposit_matches_oracle_and_is_order_independent(sr, ctx, ng, n, L):
+    rng = np.random.default_rng(n)
+    pos = (rng.random((n, 3)) * L).astype(np.float32)
+    pos[pos >= np.float32(L)] = 0
+    m = rng.uniform(0.25, 3.0, n).astype(np.float32)
+    rho, t, tm, pmh = _deposit_check(sr, ctx, pos, m, ng, L)
+    try:
+        perm = rng.permutation(n)
+        rho2 = pmh.deposit(*[_dev(pos[perm, d]) for d in range(3)], _dev(m[perm]))
+        ctx.sync()
+        assert torch.equal(rho, rho2), "deposit depends on particle order"
+    finally:
+        pmh.close()
+
+
+def test_deposit_edges(sr, ctx):
+    """Grid points, the box faces, wrapped positions outside [0, L), zero
+    masses and an empty call."""
+    ng, L = 16, 16.0
+    pos = np.array([[0, 0, 0], [15.999999, 15.999999, 15.999999], [3, 4, 5], [8.5, 8.5, 8.5],
+                    [-0.25, 17.5, 33.0], [2.75, 0.0, 15.0]], np.float32)
+    m = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 0.0], np.float32)
+    _, _, _, pmh = _deposit_check(sr, ctx, pos, m, ng, L)
+    try:
+        e = torch.zeros(0, dtype=torch.float32, device="cuda:0")
+        rho = pmh.deposit(e, e, e, e)
+        ctx.sync()
+        assert float(rho.abs().max()) == 0.0
+    finally:
+        pmh.close()
+
+
+def test_bad_inputs(sr, ctx):
+    for ng in (4, 12, 2048):
+        with pytest.raises(sr.SRError):
+            sr.PM(ctx, ng, 10.0)
+    with pytest.raises(sr.SRError):
+        sr.PM(ctx, 16, -1.0)
+    pmh = sr.PM(ctx, 16, 16.0)
+    try:
+        x = _dev(np.ones(4, np.float32))
+        m = _dev(np.array([1.0, -1.0, 1.0, 1.0], np.float32))
+        pmh.force(x, x, x, m)
+        with pytest.raises(sr.SRError):
+            ctx.sync()
+        bad = _dev(np.array([1.0, np.nan, 1.0, 1.0], np.float32))
+        pmh.force(bad, x, x, _dev(np.ones(4, np.float32)))
+        with pytest.raises(sr.SRError):
+            ctx.sync()
+        ctx.sync()  # status cleared
+    finally:
+        pmh.close()
+
+
+def _force_case(sr, ctx, pos32, m, ng, L, label, targets=None):
+    pmh = sr.PM(ctx, ng, L)
+    try:
+        t = [_dev(pos32[:, d]) for d in range(3)]
+        a = pmh.force(*t, _dev(m))
+        ctx.sync()
+        a1 = _np(*a)
+        a2 = _np(*pmh.force(*t, _dev(m)))
+        ctx.sync()
+        assert np.array_equal(a1, a2), "PM force not reproducible"
+    finally:
+        pmh.close()
+    ref = PMO.pm_accel(pos32.astype(np.float64), m.astype(np.float64), ng, L, targets=targets)
+    got = a1 if targets is None else a1[targets]
+    check_pm_accel(got, ref, label)
+    return a1
+
+
+def test_force_uniform_and_mixed_masses(sr, ctx):
+    rng = np.random.default_rng(1)
+    L, ng, n = 32.0, 32, 30000
+    pos = (rng.random((n, 3)) * L).astype(np.float32)
+    m = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    a = _force_case(sr, ctx, pos, m, ng, L, "uniform 32^3")
+    tot = (m.astype(np.float64)[:, None] * a).sum(0)
+    assert np.abs(tot).max() <= 1e-5 * (m[:, None] * np.abs(a)).sum()
+
+
+def test_force_clustered_and_zeldovich(sr, ctx):
+    c = W.nfw_share(40000, 48.0, 3, periodic=True, halo_cap=15000)
+    pos = np.stack([c.x, c.y, c.z], 1)
+    _force_case(sr, ctx, pos, c.m, 64, 48.0, "clustered 64^3 grid")
+    z = W.zeldovich(32, 32.0, 4)
+    pos = np.stack([z.x, z.y, z.z], 1)
+    _force_case(sr, ctx, pos, z.m, 32, 32.0, "zeldovich 32^3")
+
+
+def test_force_test_pair_matches_paper_fit(sr, ctx):
+    """Many independent source / massless test pairs cannot share one grid,
+    so this runs pairs one by one on a 64^3 grid and compares the radial
+    mean at r = 2 and 4 grid cells with Eq. (fitform)."""
+    ng = 64
+    pmh = sr.PM(ctx, ng, float(ng))
+    try:
+        rng = np.random.default_rng(9)
+        for r in (2.0, 4.0):
+            vals = []
+            for _ in range(24):
+                c = rng.random(3) * ng
+                u = rng.normal(size=3)
+                u /= np.linalg.norm(u)
+                pos = np.stack([c, np.mod(c + r * u, ng)]).astype(np.float32)
+                a = pmh.force(*[_dev(pos[:, d]) for d in range(3)],
+                              _dev(np.array([1.0, 0.0], np.float32)))
+                ctx.sync()
+                vals.append(-float(np.dot(_np(*a)[1], u)))
+            vals = np.asarray(vals)
+            want = float(gridfit.f_grid(r))
+            assert abs(vals.mean() - want) <= 3 * vals.std() / np.sqrt(vals.size) + 0.025 * want
+    finally:
+        pmh.close()
+
+
+def test_force_full_size_zeldovich128_sampled(sr, ctx):
+    """The 128^3 Zel'dovich box on a 128^3 grid (the configuration the step
+    bench times): 2048 sampled particles against the oracle, and Newton's
+    third law over all 2^21 particles."""
+    p = W.config("zeldovich128")
+    pos = np.stack([p.x, p.y, p.z], 1)
+    tg = np.sort(np.random.default_rng(3).choice(p.n, 2048, replace=False))
+    a = _force_case(sr, ctx, pos, p.m, 128, float(p.L),
+                    "zeldovich128 sampled", targets=tg)
+    tot = (p.m.astype(np.float64)[:, None] * a).sum(0)
+    assert np.abs(tot).max() <= 1e-5 * (p.m[:, None] * np.abs(a)).sum()
+
+
+def test_force_split_matches_oracle_on_f64_masters(sr, ctx):
+    L, ng, cell = 24.0, 32, 3.0
+    pos = np.random.default_rng(6).random((20000, 3)) * L
+    m = np.random.default_rng(7).uniform(0.5, 2.0, 20000).astype(np.float32)
+    box = sr.Box.make(L)
+    x, y, z = [_dev(pos[:, d], torch.float64) for d in range(3)]
+    c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+    pmh = sr.PM(ctx, ng, L)
+    try:
+        a = pmh.force_split(c3, ox, oy, oz, _dev(m), cell)
+        ctx.sync()
+    finally:
+        pmh.close()
+    check_pm_accel(_np(*a), PMO.pm_accel(pos, m.astype(np.float64), ng, L), "split")
+
+
+R_MAX, EPS = 3.0, 0.1
+
+
+def _wrapdiff(a, b, L):
+    d = a - b
+    return d - L * np.round(d / L)
+
+
+def test_ksk_step_matches_oracle(sr, ctx):
+    """Two full steps (n_sub = 3) of a small periodic box: positions and
+    velocities against the FP64 oracle step; the second step reuses the first
+    step's outgoing PM force (lr_valid)."""
+    L, ng, cell, n = 16.0, 16, 3.0, 3000
+    rng = np.random.default_rng(21)
+    pos = rng.random((n, 3)) * L
+    vel = rng.normal(scale=0.2, size=(n, 3)).astype(np.float32)
+    m = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    poly = gridfit.poly_coeffs()
+    box = sr.Box.make(L)
+    x, y, z = [_dev(pos[:, d], torch.float64) for d in range(3)]
+    c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+    st = {"cell3": c3, "ox": ox, "oy": oy, "oz": oz, "vx": _dev(vel[:, 0]), "vy": _dev(vel[:, 1]),
+          "vz": _dev(vel[:, 2]), "m": _dev(m)}
+    lr = tuple(torch.zeros(n, dtype=torch.float32, device="cuda:0") for _ in range(3))
+    sro = tuple(torch.zeros(n, dtype=torch.float32, device="cuda:0") for _ in range(3))
+    pmh = sr.PM(ctx, ng, L)
+    dt = 0.05
+    prm = sr.StepParams.make(R_MAX, EPS, poly, cell, dt, 3)
+    P, V, alr = pos.copy(), vel.astype(np.float64), None
+    try:
+        for step in range(2):
+            sr.sr_ksk_step(ctx, pmh, st, box, prm, lr, step > 0, sro)
+            ctx.sync()
+            P, V, alr, asr = PMO.ksk_step(P, V, m, L, ng, R_MAX, EPS, poly.astype(np.float64), dt,
+                                          3, a_lr=alr)
+            gx, gy, gz = sr.sr_split_to_f64(ctx, c3, ox, oy, oz, box, cell)
+            ctx.sync()
+            gp = torch.stack([gx, gy, gz], 1).cpu().numpy()
+            gv = _np(st["vx"], st["vy"], st["vz"])
+            vs = np.sqrt((V ** 2).sum(1).mean())
+            dv = np.abs(gv - V).max()
+            dx = np.abs(_wrapdiff(gp, P, L)).max()
+            print("step %d: max|dv| %.3e (rms v %.3e), max|dx| %.3e" % (step, dv, vs, dx))
+            assert dv <= 2e-5 * vs + 1e-4 * dt * np.abs(alr).max(), step
+            assert dx <= 2e-5 * dt * vs + 1e-6, step
+            check_pm_accel(_np(*lr), alr, "step %d a_lr" % step)
+    finally:
+        pmh.close()
+
+
+def test_ksk_step_rejects_mismatched_box(sr, ctx):
+    pmh = sr.PM(ctx, 16, 16.0)
+    try:
+        n = 8
+        z = lambda dt=torch.float32: torch.zeros(n, dtype=dt, device="cuda:0")
+        st = {"cell3": z(torch.int32), "ox": z(), "oy": z(), "oz": z(), "vx": z(), "vy": z(),
+              "vz": z(), "m": z()}
+        prm = sr.StepParams.make(R_MAX, EPS, gridfit.poly_coeffs(), 3.0, 0.1, 2)
+        with pytest.raises(sr.SRError):
+            sr.sr_ksk_step(ctx, pmh, st, sr.Box.make(17.0), prm, (z(), z(), z()), 0,
+                           (z(), z(), z()))
+        with pytest.raises(sr.SRError):
+            sr.sr_ksk_step(ctx, pmh, st, sr.Box.make((16.0, 16.0, 32.0)), prm, (z(), z(), z()),
+                           0, (z(), z(), z()))
+        bad = sr.StepParams.make(R_MAX, EPS, gridfit.poly_coeffs(), 3.0, 0.1, 0)
+        with pytest.raises(sr.SRError):
+            sr.sr_ksk_step(ctx, pmh, st, sr.Box.make(16.0), bad, (z(), z(), z()), 0,
+                           (z(), z(), z()))
+    finally:
+        pmh.close()
