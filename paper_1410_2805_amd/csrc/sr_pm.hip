@@ -2,14 +2,20 @@
 //
 //   deposit   CIC weights from FP64 grid coordinates; every particle adds its
 //             8 contributions to a 64-bit fixed-point grid with integer
-//             atomics, so the density is independent of arrival order.
+//             atomics (neighbouring lanes share their common corners
+//             first), so the density is independent of arrival order.
 //   FFT       radix-4 (and one radix-2) Stockham passes in LDS along z, y
-//             and x; the twiddles are an FP64-built float32 table.
-//   k space   one kernel applies 4 pi G_6 S (Eqs. (greenf), (filter)) and
-//             the Super-Lanczos gradient (Eq. (sldiff)), writing two spectra:
-//             A_x + i A_y and A_z.  Each A_d is the transform of a real field,
-//             so one complex inverse FFT returns a_x and a_y together.
+//             and x; the twiddles are an FP64-built float32 table.  The
+//             first pass reads the fixed-point sums directly.
+//   k space   applied inside the x pass, between its forward and inverse
+//             transforms: 4 pi G_6 S (Eqs. (greenf), (filter)) and the
+//             Super-Lanczos gradient (Eq. (sldiff)) give two spectra, A_x +
+//             i A_y and A_z.  Each A_d is the transform of a real field, so
+//             one complex inverse FFT returns a_x and a_y together.
 //   interp    CIC gather of (a_x, a_y, a_z) at each particle.
+//
+// Eight launches per force: mass maximum, deposit, z, y, x (forward, k
+// space, inverse), y and z (inverse, both grids), interpolation.
 //
 // All k-space factors are separable per axis except the G_6 sum; per-axis
 // tables are built in FP64 on the host.  The G_6 axis term is stored minus
@@ -29,10 +35,11 @@ struct sr_pm {
     float sigma = 0.f;
     int ns = 0;
     float2 *ga = nullptr;   // complex grid; density, then A_x + i A_y
-    float2 *gb = nullptr;   // complex grid; 64-bit deposit accumulator, then A_z
+    float2 *gb = nullptr;   // complex grid; A_z
+    unsigned long long *acc = nullptr;  // 64-bit fixed-point deposit, zero between calls
     float2 *tw = nullptr;   // [ng] exp(-2 pi i m / ng)
     float *tab = nullptr;   // [3 ng] G_6 axis term, filter factor, gradient factor
-    unsigned *mmax = nullptr;  // [1] bit pattern of the largest mass
+    unsigned *part = nullptr;  // per-block maxima of the masses (bit patterns)
 };
 
 namespace {
@@ -105,116 +112,171 @@ __device__ __forceinline__ int fixed_shift(unsigned mbits, int n)
     return 62 - em - en;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pm_clear(unsigned long long *__restrict__ acc,
-                                                     long long count, unsigned *__restrict__ mmax)
+__device__ __forceinline__ unsigned wave_max(unsigned v)
 {
-    const long long stride = (long long)gridDim.x * kBlock;
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride)
-        acc[i] = 0ull;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *mmax = 0u;
-}
-
-// Largest mass (bit pattern of a non-negative float orders like the value);
-// a negative or non-finite mass sets the status.
-__global__ __launch_bounds__(kBlock) void k_pm_mass_max(const float *__restrict__ m, int n,
-                                                        unsigned *__restrict__ mmax,
-                                                        int *__restrict__ status)
-{
-    __shared__ unsigned part[kBlock / 64];
-    unsigned v = 0u;
-    bool bad = false;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const float mi = m[i];
-        if (!(mi >= 0.f) || !isfinite(mi))
-            bad = true;
-        else
-            v = max(v, __float_as_uint(mi));
-    }
-    if (bad)
-        atomicOr(status, kStatusMass);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
         v = max(v, (unsigned)__shfl_xor((int)v, off));
+    return v;
+}
+
+// Largest mass from the per-block partial maxima (wave-uniform result).
+__device__ __forceinline__ unsigned parts_max(const unsigned *__restrict__ part, int nparts)
+{
+    unsigned v = 0u;
+    for (int k = threadIdx.x & 63; k < nparts; k += 64)
+        v = max(v, part[k]);
+    return wave_max(v);
+}
+
+// Per-block maxima of the masses (the bit pattern of a non-negative float
+// orders like its value); a negative or non-finite mass sets the status.
+// No atomics on one word: each block writes its own partial.  Each thread
+// keeps kMaxUnroll independent loads in flight.
+constexpr int kMaxUnroll = 8;
+
+__global__ __launch_bounds__(kBlock) void k_pm_mass_max(const float *__restrict__ m, int n,
+                                                        unsigned *__restrict__ part,
+                                                        int *__restrict__ status)
+{
+    __shared__ unsigned sh[kBlock / 64];
+    unsigned v = 0u;
+    bool bad = false;
+    for (int base = blockIdx.x * kBlock * kMaxUnroll + threadIdx.x; base < n;
+         base += gridDim.x * kBlock * kMaxUnroll) {
+        float mv[kMaxUnroll];
+#pragma unroll
+        for (int u = 0; u < kMaxUnroll; ++u) {
+            const int i = base + u * kBlock;
+            mv[u] = i < n ? m[i] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kMaxUnroll; ++u) {
+            if (!(mv[u] >= 0.f) || !isfinite(mv[u]))
+                bad = true;
+            else
+                v = max(v, __float_as_uint(mv[u]));
+        }
+    }
+    if (bad)
+        atomicOr(status, kStatusMass);
+    v = wave_max(v);
     if ((threadIdx.x & 63) == 0)
-        part[threadIdx.x >> 6] = v;
+        sh[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned b = part[0];
+        unsigned b = sh[0];
         for (int w = 1; w < kBlock / 64; ++w)
-            b = max(b, part[w]);
-        atomicMax(mmax, b);
+            b = max(b, sh[w]);
+        part[blockIdx.x] = b;
     }
 }
 
+__device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long v, int d)
+{
+    const int lo = __shfl_up((int)(unsigned)v, d), hi = __shfl_up((int)(unsigned)(v >> 32), d);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Deposit: one particle per lane, 8 fixed-point contributions each, added
+// to the grid with 64-bit integer atomics.  Along z, the upper corners of
+// lane k are the lower corners of lane k + 1 whenever the two particles sit
+// in neighbouring cells of one (x, y) column (the common case for inputs in
+// lattice or cell order), so lane k + 1 takes those four values over by a
+// lane shuffle and one atomic serves both.  Integer sums make the result
+// independent of every order.
 template <class Src>
 __global__ __launch_bounds__(kBlock) void k_pm_deposit(Src src, const float *__restrict__ m, int n,
-                                                       PmGeo g, const unsigned *__restrict__ mmax,
+                                                       PmGeo g, const unsigned *__restrict__ part,
+                                                       int nparts,
                                                        unsigned long long *__restrict__ acc,
                                                        int *__restrict__ status)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n)
-        return;
-    double p[3], f[3];
-    int i0[3], i1[3];
-    src.get(i, p);
-    if (!cic_setup(p, g, i0, i1, f)) {
-        atomicOr(status, kStatusMass);
-        return;
+    const int lane = threadIdx.x & 63;
+    const int shift = fixed_shift(parts_max(part, nparts), n);
+    bool ok = false;
+    double f[3] = {0.0, 0.0, 0.0};
+    int i0[3] = {0, 0, 0}, i1[3] = {0, 0, 0};
+    double q = 0.0;
+    if (i < n) {
+        double p[3];
+        src.get(i, p);
+        if (!cic_setup(p, g, i0, i1, f)) {
+            atomicOr(status, kStatusMass);
+        } else {
+            const float mi = m[i];
+            if (mi >= 0.f && isfinite(mi) && mi != 0.f) {
+                ok = true;
+                q = ldexp((double)mi, shift);
+            }
+        }
     }
-    const float mi = m[i];
-    if (!(mi >= 0.f) || !isfinite(mi) || mi == 0.f)
-        return;
-    const double q = ldexp((double)mi, fixed_shift(*mmax, n));
-    const double wx[2] = {1.0 - f[0], f[0]}, wy[2] = {1.0 - f[1], f[1]},
-                 wz[2] = {1.0 - f[2], f[2]};
-    const int ix[2] = {i0[0], i1[0]}, iy[2] = {i0[1], i1[1]}, iz[2] = {i0[2], i1[2]};
+    const double wx[2] = {1.0 - f[0], f[0]}, wy[2] = {1.0 - f[1], f[1]};
+    const double wz0 = 1.0 - f[2], wz1 = f[2];
+    const int ix[2] = {i0[0], i1[0]}, iy[2] = {i0[1], i1[1]};
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
+            const int row = (ix[a] * g.ng + iy[b]) * g.ng;
             const double qab = q * wx[a] * wy[b];
-            const long long row = ((long long)ix[a] * g.ng + iy[b]) * g.ng;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const unsigned long long v = (unsigned long long)llrint(qab * wz[c]);
-                if (v)
-                    atomicAdd(acc + row + iz[c], v);
-            }
+            unsigned long long v0 = ok ? (unsigned long long)llrint(qab * wz0) : 0ull;
+            const unsigned long long v1 = ok ? (unsigned long long)llrint(qab * wz1) : 0ull;
+            const int k0 = ok ? row + i0[2] : -1, k1 = ok ? row + i1[2] : -2;
+            const int rk = __shfl_up(k1, 1);
+            const unsigned long long rv = shfl_up_u64(v1, 1);
+            const bool take = lane > 0 && rk == k0;
+            if (take)
+                v0 += rv;
+            const bool given = __shfl_down((int)take, 1) != 0 && lane < 63;
+            if (v0)
+                atomicAdd(acc + k0, v0);
+            if (v1 && !given)
+                atomicAdd(acc + k1, v1);
         }
 }
 
-// Fixed-point sums -> density (mass / Delta^3): complex (rho, 0) into a grid
-// or plain float32 into an output array.
-__global__ __launch_bounds__(kBlock) void k_pm_density(const unsigned long long *__restrict__ acc,
+// Fixed-point sums -> density (mass / Delta^3) as float32, clearing the
+// accumulator for the next call.
+__global__ __launch_bounds__(kBlock) void k_pm_density(unsigned long long *__restrict__ acc,
                                                        long long count,
-                                                       const unsigned *__restrict__ mmax, int n,
-                                                       double inv_vol, float2 *__restrict__ outc,
-                                                       float *__restrict__ outr)
+                                                       const unsigned *__restrict__ part,
+                                                       int nparts, int n, double inv_vol,
+                                                       float *__restrict__ out)
 {
-    const double unit = ldexp(inv_vol, -fixed_shift(*mmax, n));
+    const double unit = ldexp(inv_vol, -fixed_shift(parts_max(part, nparts), n));
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
-        const float r = (float)((double)acc[i] * unit);
-        if (outc)
-            outc[i] = make_float2(r, 0.f);
-        else
-            outr[i] = r;
+        out[i] = (float)((double)acc[i] * unit);
+        acc[i] = 0ull;
     }
 }
 
 // ---- FFT ---------------------------------------------------------------
 // One block transforms `lines` whole lines of one axis.  Lines of the y and
 // x passes are taken consecutive in z, so each row of the block's tile is a
-// contiguous run of `lines` complex values in memory.
+// contiguous run of `lines` complex values in memory.  Two fusions:
+//   * the forward z pass may read the fixed-point accumulator directly
+//     (converting to density and clearing it);
+//   * the x pass may run forward, apply the k-space factors, and run the
+//     inverse transform of both output spectra before storing them.
 
 struct FftPass {
-    float2 *data[2];
+    float2 *data[2];   // field of blockIdx.y (plain passes)
     const float2 *tw;
     int ng, log2ng, lines, log2lines;
-    int axis;      // 0: x (stride ng^2), 1: y (stride ng), 2: z (stride 1)
+    int axis;          // 0: x (stride ng^2), 1: y (stride ng), 2: z (stride 1)
     int inverse;
+    // forward z pass from the accumulator (acc != nullptr)
+    unsigned long long *acc;
+    const unsigned *part;
+    int nparts, n;
+    double inv_vol;
+    // fused k space on the x pass (tab != nullptr): data[0] in, data[0] and
+    // data[1] out
+    const float *tab;
+    float g6num, norm;
 };
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
@@ -236,41 +298,42 @@ __device__ __forceinline__ long long fft_addr(const FftPass &P, long long line, 
     return ((long long)e << (2 * P.log2ng)) + (hi << P.log2ng) + lo;
 }
 
-__global__ __launch_bounds__(kFftThreads) void k_fft_lines(FftPass P)
+__device__ __forceinline__ void tile_pos(const FftPass &P, int t, int &j, int &e)
 {
-    extern __shared__ float2 tile[];
-    float2 *__restrict__ data = P.data[blockIdx.y];
-    const int ng = P.ng, ld = ng + 1;
-    const int tot = P.lines << P.log2ng;
-    const long long line0 = (long long)blockIdx.x * P.lines;
-    const int tid = threadIdx.x;
-    for (int t = tid; t < tot; t += kFftThreads) {
-        int j, e;
-        if (P.axis == 2) {
-            j = t >> P.log2ng;
-            e = t & (ng - 1);
-        } else {
-            j = t & (P.lines - 1);
-            e = t >> P.log2lines;
-        }
-        tile[j * ld + e] = data[fft_addr(P, line0 + j, e)];
+    if (P.axis == 2) {
+        j = t >> P.log2ng;
+        e = t & (P.ng - 1);
+    } else {
+        j = t & (P.lines - 1);
+        e = t >> P.log2lines;
     }
-    __syncthreads();
+}
 
-    const float sgn = P.inverse ? 1.f : -1.f;  // sign of the exponent
+// All Stockham stages on ntile (1 or 2) tiles of `lines` rows each, tile t at
+// tile + t * tstride, row stride ld.  Radix 2 first when log2 ng is odd, then
+// radix 4; natural order in and out.  Every thread of the block must call.
+constexpr int kMaxTiles = 2;
+
+__device__ void fft_stages(float2 *tile, int tstride, int ntile, const FftPass &P, int inverse)
+{
+    const int ng = P.ng, ld = ng + 1, tid = threadIdx.x;
+    const int per_tile = P.lines << P.log2ng;
+    const float sgn = inverse ? 1.f : -1.f;  // sign of the exponent
     int ns = 1;
-    if (P.log2ng & 1) {  // one radix-2 stage (ns = 1: no twiddles)
-        constexpr int kMax = kFftElems / 2 / kFftThreads;
+    if (P.log2ng & 1) {
+        constexpr int kMax = kMaxTiles * kFftElems / 2 / kFftThreads;
         float2 v[kMax][2];
-        const int nb = tot >> 1, half = ng >> 1;
+        const int nbt = per_tile >> 1, nb = nbt * ntile, half = ng >> 1;
 #pragma unroll
         for (int c = 0; c < kMax; ++c) {
             const int bb = tid + c * kFftThreads;
             if (bb >= nb)
                 break;
-            const int j = bb >> (P.log2ng - 1), b = bb & (half - 1);
-            v[c][0] = tile[j * ld + b];
-            v[c][1] = tile[j * ld + b + half];
+            const int t = bb >= nbt, r = bb - t * nbt;
+            const float2 *row = tile + t * tstride + (r >> (P.log2ng - 1)) * ld;
+            const int b = r & (half - 1);
+            v[c][0] = row[b];
+            v[c][1] = row[b + half];
         }
         __syncthreads();
 #pragma unroll
@@ -278,27 +341,31 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(FftPass P)
             const int bb = tid + c * kFftThreads;
             if (bb >= nb)
                 break;
-            const int j = bb >> (P.log2ng - 1), b = bb & (half - 1);
-            tile[j * ld + 2 * b] = cadd(v[c][0], v[c][1]);
-            tile[j * ld + 2 * b + 1] = csub(v[c][0], v[c][1]);
+            const int t = bb >= nbt, r = bb - t * nbt;
+            float2 *row = tile + t * tstride + (r >> (P.log2ng - 1)) * ld;
+            const int b = r & (half - 1);
+            row[2 * b] = cadd(v[c][0], v[c][1]);
+            row[2 * b + 1] = csub(v[c][0], v[c][1]);
         }
         __syncthreads();
         ns = 2;
     }
     for (; ns < ng; ns <<= 2) {
-        constexpr int kMax = kFftElems / 4 / kFftThreads;
+        constexpr int kMax = kMaxTiles * kFftElems / 4 / kFftThreads;
         float2 v[kMax][4];
-        const int nb = tot >> 2, q = ng >> 2, log2q = P.log2ng - 2;
+        const int nbt = per_tile >> 2, nb = nbt * ntile, q = ng >> 2, log2q = P.log2ng - 2;
         const int tw_step = ng / (ns * 4);
 #pragma unroll
         for (int c = 0; c < kMax; ++c) {
             const int bb = tid + c * kFftThreads;
             if (bb >= nb)
                 break;
-            const int j = bb >> log2q, b = bb & (q - 1);
+            const int t = bb >= nbt, r = bb - t * nbt;
+            const float2 *row = tile + t * tstride + (r >> log2q) * ld;
+            const int b = r & (q - 1);
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                v[c][r] = tile[j * ld + b + r * q];
+            for (int k = 0; k < 4; ++k)
+                v[c][k] = row[b + k * q];
         }
         __syncthreads();
 #pragma unroll
@@ -306,13 +373,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(FftPass P)
             const int bb = tid + c * kFftThreads;
             if (bb >= nb)
                 break;
-            const int j = bb >> log2q, b = bb & (q - 1);
+            const int t = bb >= nbt, r = bb - t * nbt;
+            float2 *row = tile + t * tstride + (r >> log2q) * ld;
+            const int b = r & (q - 1);
             const int k = b & (ns - 1);
             float2 x0 = v[c][0], x1 = v[c][1], x2 = v[c][2], x3 = v[c][3];
             if (k) {
                 const int m = k * tw_step;
                 float2 w1 = P.tw[m], w2 = P.tw[2 * m], w3 = P.tw[3 * m];
-                if (P.inverse) {
+                if (inverse) {
                     w1.y = -w1.y;
                     w2.y = -w2.y;
                     w3.y = -w3.y;
@@ -325,7 +394,6 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(FftPass P)
             const float2 b0 = cadd(x1, x3), d = csub(x1, x3);
             const float2 b1 = make_float2(-sgn * d.y, sgn * d.x);  // d * (sgn i)
             const int o = ((b - k) << 2) + k;
-            float2 *row = tile + j * ld;
             row[o] = cadd(a0, b0);
             row[o + ns] = cadd(a1, b1);
             row[o + 2 * ns] = csub(a0, b0);
@@ -333,40 +401,72 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(FftPass P)
         }
         __syncthreads();
     }
-
-    for (int t = tid; t < tot; t += kFftThreads) {
-        int j, e;
-        if (P.axis == 2) {
-            j = t >> P.log2ng;
-            e = t & (ng - 1);
-        } else {
-            j = t & (P.lines - 1);
-            e = t >> P.log2lines;
-        }
-        data[fft_addr(P, line0 + j, e)] = tile[j * ld + e];
-    }
 }
 
-// rho(k) -> A_x + i A_y (in place) and A_z: a(k) = -D(k) phi(k),
-// phi = 4 pi G_6 S rho / ng^3 (the inverse transforms are unnormalised).
-__global__ __launch_bounds__(kBlock) void k_pm_kspace(float2 *__restrict__ ga,
-                                                      float2 *__restrict__ gb,
-                                                      const float *__restrict__ tab, int ng,
-                                                      int log2ng, float g6num, float norm)
+__global__ __launch_bounds__(kFftThreads) void k_fft_lines(FftPass P)
 {
-    const long long total = 1ll << (3 * log2ng);
-    const long long stride = (long long)gridDim.x * kBlock;
-    const float *e6 = tab, *fl = tab + ng, *dl = tab + 2 * ng;
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) {
-        const int z = (int)(i & (ng - 1)), y = (int)((i >> log2ng) & (ng - 1)),
-                  x = (int)(i >> (2 * log2ng));
-        const float den = e6[x] + e6[y] + e6[z];
-        const float c = den < 0.f ? g6num / den * (fl[x] * fl[y] * fl[z]) * norm : 0.f;
-        const float2 r = ga[i];
-        const float px = r.x * c, py = r.y * c;  // phi
-        const float dx = dl[x], dy = dl[y], dz = dl[z];
-        ga[i] = make_float2(fmaf(px, dy, py * dx), fmaf(py, dy, -px * dx));
-        gb[i] = make_float2(dz * py, -dz * px);
+    extern __shared__ float2 tile[];
+    const int ng = P.ng, ld = ng + 1;
+    const int tot = P.lines << P.log2ng;
+    const int tstride = P.lines * ld;
+    const long long line0 = (long long)blockIdx.x * P.lines;
+    const int tid = threadIdx.x;
+
+    if (P.acc) {  // forward z pass straight from the fixed-point sums
+        const double unit = ldexp(P.inv_vol, -fixed_shift(parts_max(P.part, P.nparts), P.n));
+        for (int t = tid; t < tot; t += kFftThreads) {
+            int j, e;
+            tile_pos(P, t, j, e);
+            const long long a = fft_addr(P, line0 + j, e);
+            tile[j * ld + e] = make_float2((float)((double)P.acc[a] * unit), 0.f);
+            P.acc[a] = 0ull;
+        }
+    } else {
+        const float2 *__restrict__ src = P.data[blockIdx.y];
+        for (int t = tid; t < tot; t += kFftThreads) {
+            int j, e;
+            tile_pos(P, t, j, e);
+            tile[j * ld + e] = src[fft_addr(P, line0 + j, e)];
+        }
+    }
+    __syncthreads();
+    fft_stages(tile, tstride, 1, P, P.inverse);
+
+    if (P.tab) {
+        // x pass: row j is the line (y, z) of the spectrum, element e = x.
+        // a(k) = -D(k) phi(k), phi = 4 pi G_6 S rho / ng^3; tile 0 receives
+        // A_x + i A_y = phi (d_y - i d_x), tile 1 A_z = -i d_z phi.
+        const float *e6 = P.tab, *fl = P.tab + ng, *dl = P.tab + 2 * ng;
+        for (int t = tid; t < tot; t += kFftThreads) {
+            const int j = t >> P.log2ng, x = t & (ng - 1);
+            const long long line = line0 + j;
+            const int y = (int)(line >> P.log2ng), z = (int)(line & (ng - 1));
+            const float den = e6[x] + e6[y] + e6[z];
+            const float c = den < 0.f ? P.g6num / den * (fl[x] * fl[y] * fl[z]) * P.norm : 0.f;
+            const float2 r = tile[j * ld + x];
+            const float px = r.x * c, py = r.y * c;
+            const float dx = dl[x], dy = dl[y], dz = dl[z];
+            tile[j * ld + x] = make_float2(fmaf(px, dy, py * dx), fmaf(py, dy, -px * dx));
+            tile[tstride + j * ld + x] = make_float2(dz * py, -dz * px);
+        }
+        __syncthreads();
+        fft_stages(tile, tstride, 2, P, 1);
+        for (int f = 0; f < 2; ++f) {
+            float2 *__restrict__ dst = P.data[f];
+            for (int t = tid; t < tot; t += kFftThreads) {
+                int j, e;
+                tile_pos(P, t, j, e);
+                dst[fft_addr(P, line0 + j, e)] = tile[f * tstride + j * ld + e];
+            }
+        }
+        return;
+    }
+
+    float2 *__restrict__ dst = P.acc ? P.data[0] : P.data[blockIdx.y];
+    for (int t = tid; t < tot; t += kFftThreads) {
+        int j, e;
+        tile_pos(P, t, j, e);
+        dst[fft_addr(P, line0 + j, e)] = tile[j * ld + e];
     }
 }
 
@@ -415,16 +515,17 @@ __global__ __launch_bounds__(kBlock) void k_pm_interp(Src src, int n, PmGeo g,
 
 // ---- host side ------------------------------------------------------------
 
+constexpr int kMaxParts = 512;  // blocks of the mass maximum
+
 int grid_blocks(long long count)
 {
     long long b = (count + kBlock - 1) / kBlock;
     return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
-int fft_enqueue(sr_pm *pm, float2 *a, float2 *b, int inverse)
+FftPass fft_pass(const sr_pm *pm, float2 *a, float2 *b, int inverse)
 {
-    sr_ctx *ctx = pm->ctx;
-    FftPass P;
+    FftPass P{};
     P.data[0] = a;
     P.data[1] = b ? b : a;
     P.tw = pm->tw;
@@ -435,16 +536,29 @@ int fft_enqueue(sr_pm *pm, float2 *a, float2 *b, int inverse)
     if (lines > nlines)
         lines = nlines;
     P.lines = (int)lines;
-    P.log2lines = 0;
     while ((1 << P.log2lines) < P.lines)
         ++P.log2lines;
     P.inverse = inverse;
-    const size_t lds = (size_t)P.lines * (pm->ng + 1) * sizeof(float2);
-    const dim3 grid((unsigned)(nlines / lines), b ? 2u : 1u);
+    return P;
+}
+
+int fft_launch(sr_pm *pm, const FftPass &P, int axis, unsigned nfield, int ntile)
+{
+    FftPass Q = P;
+    Q.axis = axis;
+    const long long nlines = (long long)pm->ng * pm->ng;
+    const size_t lds = (size_t)ntile * P.lines * (pm->ng + 1) * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(nlines / P.lines), nfield),
+                       dim3(kFftThreads), lds, pm->ctx->stream, Q);
+    return sr_check_launch(pm->ctx, "k_fft_lines");
+}
+
+// Plain in-place 3-D transform of one grid.
+int fft_enqueue(sr_pm *pm, float2 *a, int inverse)
+{
+    const FftPass P = fft_pass(pm, a, nullptr, inverse);
     for (int axis = 2; axis >= 0; --axis) {
-        P.axis = axis;
-        hipLaunchKernelGGL(k_fft_lines, grid, dim3(kFftThreads), lds, ctx->stream, P);
-        int rc = sr_check_launch(ctx, "k_fft_lines");
+        int rc = fft_launch(pm, P, axis, 1, 1);
         if (rc)
             return rc;
     }
@@ -460,31 +574,33 @@ PmGeo pm_geo(const sr_pm *pm)
     return g;
 }
 
+int parts_for(int n)
+{
+    int b = (n + kMaxUnroll * kBlock - 1) / (kMaxUnroll * kBlock);
+    return b < 1 ? 1 : (b > kMaxParts ? kMaxParts : b);
+}
+
+// Mass maximum and the fixed-point deposit into pm->acc; returns the number
+// of mass partials written (0 for n == 0).
 template <class Src>
-int deposit_enqueue(sr_pm *pm, const Src &src, const float *m, int n, float *rho_out)
+int deposit_enqueue(sr_pm *pm, const Src &src, const float *m, int n, int *nparts)
 {
     sr_ctx *ctx = pm->ctx;
-    const long long cells = 1ll << (3 * pm->log2ng);
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(pm->gb);
-    hipLaunchKernelGGL(k_pm_clear, dim3(grid_blocks(cells)), dim3(kBlock), 0, ctx->stream, acc,
-                       cells, pm->mmax);
-    int rc = sr_check_launch(ctx, "k_pm_clear");
+    *nparts = 0;
+    if (n <= 0)
+        return SR_OK;
+    const int np = parts_for(n);
+    hipLaunchKernelGGL(k_pm_mass_max, dim3(np), dim3(kBlock), 0, ctx->stream, m, n, pm->part,
+                       ctx->status);
+    int rc = sr_check_launch(ctx, "k_pm_mass_max");
     if (rc)
         return rc;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_pm_mass_max, dim3(grid_blocks(n) < 1024 ? grid_blocks(n) : 1024),
-                           dim3(kBlock), 0, ctx->stream, m, n, pm->mmax, ctx->status);
-        if ((rc = sr_check_launch(ctx, "k_pm_mass_max")))
-            return rc;
-        hipLaunchKernelGGL(k_pm_deposit<Src>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                           ctx->stream, src, m, n, pm_geo(pm), pm->mmax, acc, ctx->status);
-        if ((rc = sr_check_launch(ctx, "k_pm_deposit")))
-            return rc;
-    }
-    const double inv_vol = 1.0 / (pm->delta * pm->delta * pm->delta);
-    hipLaunchKernelGGL(k_pm_density, dim3(grid_blocks(cells)), dim3(kBlock), 0, ctx->stream, acc,
-                       cells, pm->mmax, n, inv_vol, rho_out ? nullptr : pm->ga, rho_out);
-    return sr_check_launch(ctx, "k_pm_density");
+    hipLaunchKernelGGL(k_pm_deposit<Src>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       ctx->stream, src, m, n, pm_geo(pm), pm->part, np, pm->acc, ctx->status);
+    if ((rc = sr_check_launch(ctx, "k_pm_deposit")))
+        return rc;
+    *nparts = np;
+    return SR_OK;
 }
 
 template <class Src>
@@ -492,19 +608,32 @@ int force_enqueue_pm(sr_pm *pm, const Src &src, const float *m, int n, float *ax
                      float *az)
 {
     sr_ctx *ctx = pm->ctx;
-    int rc = deposit_enqueue(pm, src, m, n, nullptr);
+    int np = 0;
+    int rc = deposit_enqueue(pm, src, m, n, &np);
     if (rc)
         return rc;
-    if ((rc = fft_enqueue(pm, pm->ga, nullptr, 0)))
+    // forward z (from the accumulator), forward y, then x: forward, k space
+    // and inverse of both spectra; inverse y and z on both grids
+    FftPass P = fft_pass(pm, pm->ga, pm->gb, 0);
+    P.acc = pm->acc;
+    P.part = pm->part;
+    P.nparts = np;
+    P.n = n;
+    P.inv_vol = 1.0 / (pm->delta * pm->delta * pm->delta);
+    if ((rc = fft_launch(pm, P, 2, 1, 1)))
+        return rc;
+    P.acc = nullptr;
+    if ((rc = fft_launch(pm, P, 1, 1, 1)))
         return rc;
     const long long cells = 1ll << (3 * pm->log2ng);
-    const float g6num = (float)(45.0 / 128.0 * pm->delta * pm->delta);
-    const float norm = (float)(4.0 * M_PI / (double)cells);
-    hipLaunchKernelGGL(k_pm_kspace, dim3(grid_blocks(cells)), dim3(kBlock), 0, ctx->stream, pm->ga,
-                       pm->gb, pm->tab, pm->ng, pm->log2ng, g6num, norm);
-    if ((rc = sr_check_launch(ctx, "k_pm_kspace")))
+    P.tab = pm->tab;
+    P.g6num = (float)(45.0 / 128.0 * pm->delta * pm->delta);
+    P.norm = (float)(4.0 * M_PI / (double)cells);
+    if ((rc = fft_launch(pm, P, 0, 1, 2)))
         return rc;
-    if ((rc = fft_enqueue(pm, pm->ga, pm->gb, 1)))
+    P.tab = nullptr;
+    P.inverse = 1;
+    if ((rc = fft_launch(pm, P, 1, 2, 1)) || (rc = fft_launch(pm, P, 2, 2, 1)))
         return rc;
     if (n <= 0)
         return SR_OK;
@@ -551,8 +680,9 @@ extern "C" int sr_pm_bytes(int32_t ng, size_t *bytes)
     if (!bytes || ng < 8 || ng > 1024 || (ng & (ng - 1)))
         return SR_EINVAL;
     const size_t cells = (size_t)ng * ng * ng;
-    *bytes = 2 * cells * sizeof(float2) + (size_t)ng * sizeof(float2) + 3 * (size_t)ng * sizeof(float) +
-             256;
+    *bytes = 2 * cells * sizeof(float2) + cells * sizeof(unsigned long long) +
+             (size_t)ng * sizeof(float2) + 3 * (size_t)ng * sizeof(float) +
+             kMaxParts * sizeof(unsigned);
     return SR_OK;
 }
 
@@ -585,7 +715,8 @@ extern "C" int sr_pm_create(sr_ctx *ctx, int32_t ng, double len, float sigma, in
               hipMalloc(&pm->gb, cells * sizeof(float2)) == hipSuccess &&
               hipMalloc(&pm->tw, ng * sizeof(float2)) == hipSuccess &&
               hipMalloc(&pm->tab, 3 * ng * sizeof(float)) == hipSuccess &&
-              hipMalloc(&pm->mmax, sizeof(unsigned)) == hipSuccess;
+              hipMalloc(&pm->acc, cells * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&pm->part, kMaxParts * sizeof(unsigned)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         sr_pm_destroy(pm);
@@ -613,7 +744,9 @@ extern "C" int sr_pm_create(sr_ctx *ctx, int32_t ng, double len, float sigma, in
         tab[ng + n] = (float)(exp(-k * k * sd * sd / 4.0) * pow(sinc, ns));
         tab[2 * ng + n] = (float)((4.0 / 3.0 * sin(h) - 1.0 / 6.0 * sin(2 * h)) / d);
     }
-    if (hipMemcpy(pm->tw, tw.data(), ng * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemset(pm->acc, 0, cells * sizeof(unsigned long long)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(pm->tw, tw.data(), ng * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(pm->tab, tab.data(), 3 * ng * sizeof(float), hipMemcpyHostToDevice) !=
             hipSuccess) {
         sr_pm_destroy(pm);
@@ -635,7 +768,8 @@ extern "C" int sr_pm_destroy(sr_pm *pm)
     (void)hipFree(pm->gb);
     (void)hipFree(pm->tw);
     (void)hipFree(pm->tab);
-    (void)hipFree(pm->mmax);
+    (void)hipFree(pm->acc);
+    (void)hipFree(pm->part);
     delete pm;
     return SR_OK;
 }
@@ -650,7 +784,14 @@ extern "C" int sr_pm_deposit(sr_pm *pm, const float *x, const float *y, const fl
         return rc;
     if (!rho)
         return sr_fail(pm->ctx, SR_EINVAL, "rho is NULL");
-    return deposit_enqueue(pm, SrcGlobal{x, y, z}, mass, (int)n, rho);
+    int np = 0;
+    if ((rc = deposit_enqueue(pm, SrcGlobal{x, y, z}, mass, (int)n, &np)))
+        return rc;
+    const long long cells = 1ll << (3 * pm->log2ng);
+    hipLaunchKernelGGL(k_pm_density, dim3(grid_blocks(cells)), dim3(kBlock), 0,
+                       pm->ctx->stream, pm->acc, cells, pm->part, np, (int)n,
+                       1.0 / (pm->delta * pm->delta * pm->delta), rho);
+    return sr_check_launch(pm->ctx, "k_pm_density");
 }
 
 extern "C" int sr_pm_fft(sr_pm *pm, float *data, int32_t inverse)
@@ -660,7 +801,7 @@ extern "C" int sr_pm_fft(sr_pm *pm, float *data, int32_t inverse)
         return rc;
     if (!data)
         return sr_fail(pm->ctx, SR_EINVAL, "data is NULL");
-    return fft_enqueue(pm, reinterpret_cast<float2 *>(data), nullptr, inverse ? 1 : 0);
+    return fft_enqueue(pm, reinterpret_cast<float2 *>(data), inverse ? 1 : 0);
 }
 
 extern "C" int sr_pm_force(sr_pm *pm, const float *x, const float *y, const float *z,
