@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="zeldovich128",
-                    choices=sorted(WORKLOADS) + ["batch64", "serving"])
+                    choices=sorted(WORKLOADS) + ["batch64", "serving", "ksk128"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
     ap.add_argument("--replays", type=int, default=200, help="batch64: timed graph replays")
     ap.add_argument("--cell", type=float, default=3.0)
@@ -128,6 +128,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "ksk128":
+        return bench_step(args)
     dev = torch.device("cuda:0")
     if args.calib_copy:
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -331,6 +333,114 @@ def bench_batch(args):
     }
     print(json.dumps(res), flush=True)
     plan.close()
+    ctx.close()
+
+
+def bench_step(args):
+    """Full steps of Eq. (tstep) on the 128^3 Zel'dovich box: split
+    coordinates from FP64 masters, a 128^3 PM grid (sigma 0.8, n_s 3) and
+    three short-range subcycles per step.  Also times one PM force alone and
+    one 3-D FFT of the grid."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2805_amd import gridfit, sr, workloads
+
+    dev = torch.device("cuda:0")
+    ng, L, cell, nsub, dt = 128, 128.0, 3.0, 3, 0.05
+    poly = gridfit.poly_coeffs()
+    log("generating the 128^3 Zel'dovich box (FP64 masters)")
+    pos = workloads.zeldovich_pos64(128, L, 2)
+    n = pos.shape[0]
+    vel = np.random.default_rng(7).normal(scale=0.3, size=(n, 3)).astype(np.float32)
+    box = sr.Box.make(L)
+    ctx = sr.Context(0, arena_bytes=sr.sr_scratch_bytes(box, cell, n, True))
+    x, y, z = [torch.from_numpy(np.ascontiguousarray(pos[:, d])).to(dev) for d in range(3)]
+    c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+    del x, y, z
+    st = {"cell3": c3, "ox": ox, "oy": oy, "oz": oz,
+          "vx": torch.from_numpy(vel[:, 0].copy()).to(dev),
+          "vy": torch.from_numpy(vel[:, 1].copy()).to(dev),
+          "vz": torch.from_numpy(vel[:, 2].copy()).to(dev),
+          "m": torch.ones(n, dtype=torch.float32, device=dev)}
+    lr = tuple(torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(3))
+    so = tuple(torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(3))
+    pm = sr.PM(ctx, ng, L)
+    prm = sr.StepParams.make(R_MAX, EPS, poly, cell, dt, nsub)
+    steps = max(1, min(args.steps, 40))
+    for k in range(args.warmup):
+        sr.sr_ksk_step(ctx, pm, st, box, prm, lr, k > 0, so)
+    ctx.sync()
+    ctx.timing_enable(True)
+    ctx.timing_collect()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        sr.sr_ksk_step(ctx, pm, st, box, prm, lr, True, so)
+    ev1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms_step = ev0.elapsed_time(ev1) / steps
+    prep_ms, force_ms, calls = ctx.timing_collect()
+    ctx.timing_enable(False)
+    force_avg = force_ms / max(calls, 1)
+    # candidate pairs at the final positions (for the pair-loop roofline)
+    gx, gy, gz = sr.sr_split_to_f64(ctx, c3, ox, oy, oz, box, cell)
+    p32 = [g.float() for g in (gx, gy, gz)]
+    for g in p32:
+        g[g >= L] = 0.0
+    useful, cand, _ = sr.sr_pair_stats(ctx, *p32, box, cell, R_MAX)
+    achieved = FLOP_PER_PAIR * cand / (force_avg * 1e-3) / 1e12
+    # PM force alone and one plain 3-D FFT
+    reps = 20
+    ev0.record()
+    for _ in range(reps):
+        pm.force_split(c3, ox, oy, oz, st["m"], cell, out=lr)
+    ev1.record()
+    torch.cuda.synchronize()
+    pm_ms = ev0.elapsed_time(ev1) / reps
+    grid = torch.zeros((ng, ng, ng), dtype=torch.complex64, device=dev)
+    ev0.record()
+    for _ in range(reps):
+        pm.fft(grid)
+    ev1.record()
+    torch.cuda.synchronize()
+    fft_ms = ev0.elapsed_time(ev1) / reps
+    fft_bytes = 3 * 2 * 8 * ng ** 3    # three passes, read + write of complex64
+    log("step %.4f ms (pair loop %.4f ms x %d per step), PM force %.4f ms, FFT %.4f ms"
+        % (ms_step, force_avg, nsub, pm_ms, fft_ms))
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import pm as PMO
+        t0 = time.perf_counter()
+        PMO.pm_accel(pos, np.ones(n), ng, L)
+        t_pm = time.perf_counter() - t0
+        cpu = {"value": n / t_pm, "unit": "PM particle accelerations/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "the FP64 numpy PM oracle on all %d particles, 128^3 grid, %.1f s "
+                         "(the short-range oracle is timed by the default bench)" % (n, t_pm)}
+    res = {
+        "metric": "full KSK step (Eq. tstep) particle updates/s",
+        "value": n / (ms_step * 1e-3),
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "128^3 Zel'dovich box (FP64 masters, split coordinates), "
+                               "PM 128^3 (sigma 0.8, n_s 3), n_sub=3, dt=0.05, r_max=3, "
+                               "eps=0.1, cell 3",
+                   "pair_loop_ms": force_avg, "pair_loop_calls_per_step": nsub,
+                   "pm_force_ms": pm_ms, "fft3d_ms": fft_ms,
+                   "fft3d_GBps": fft_bytes / (fft_ms * 1e-3) / 1e9,
+                   "candidate_pairs_final": cand, "useful_pairs_final": useful},
+        "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved,
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    pm.close()
     ctx.close()
 
 

@@ -290,3 +290,41 @@ def config(name: str) -> Particles:
     if name == "nfw256":
         return nfw_share(256 ** 3, 256.0, 3, skin=3.0)
     raise KeyError(name)
+
+
+@dataclasses.dataclass
+class PairSet:
+    """One unit-mass source (index 0) and massless test particles around it
+    in a periodic cube of side L: float32 positions, masses, and the FP64
+    separation r and unit direction u (source -> test) of each test particle
+    as the float32 positions realise them (minimum image)."""
+
+    pos: np.ndarray   # (1 + ntest, 3) float32
+    m: np.ndarray     # (1 + ntest,) float32: 1, 0, 0, ...
+    r: np.ndarray     # (ntest,) float64
+    u: np.ndarray     # (ntest, 3) float64
+    L: float
+
+
+def pm_test_pairs(nsrc: int, ntest: int, L: float, r_max: float, seed: int,
+                  r_lo: float = 0.02) -> list:
+    """Seeded test-pair sets for measuring the filtered grid force (the
+    experiment of Sec. 2.3): each set has a source at a uniformly random
+    position and ntest massless particles at separations uniform in
+    [r_lo, r_max] with isotropic directions."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nsrc):
+        c = rng.random(3) * L
+        r = rng.uniform(r_lo, r_max, ntest)
+        u = rng.normal(size=(ntest, 3))
+        u /= np.linalg.norm(u, axis=1)[:, None]
+        pos = np.mod(np.vstack([c[None, :], c[None, :] + r[:, None] * u]), L).astype(np.float32)
+        pos[pos >= np.float32(L)] = 0
+        d = pos[1:].astype(np.float64) - pos[0].astype(np.float64)
+        d -= L * np.round(d / L)
+        rr = np.linalg.norm(d, axis=1)
+        m = np.zeros(ntest + 1, np.float32)
+        m[0] = 1.0
+        out.append(PairSet(pos, m, rr, d / rr[:, None], float(L)))
+    return out

@@ -200,3 +200,23 @@ def test_ksk_second_order_against_fine_leapfrog():
         errs.append(np.abs(_wrapdiff(q, p, L)).max())
     assert errs[1] < errs[0]
     assert 2.5 < errs[0] / errs[1] < 6.0, errs
+
+
+def test_polynomial_regenerated_from_pm_matches_fitform():
+    """The polynomial refitted from FP64 PM test pairs (Sec. 2.4 recipe)
+    reproduces the paper's printed fit of the grid force to a few percent
+    over the whole short-range interval, and its residual is the
+    orientation (anisotropy) scatter, not a bias."""
+    from oracle import pmfit
+    from paper_1410_2805_amd import workloads as W
+    sets = W.pm_test_pairs(16, 2048, 64.0, 3.0, 17)
+    r, f = pmfit.radial_samples(sets, 64)
+    c = pmfit.fit(r, f)
+    rr = np.linspace(0.1, 2.9, 57)
+    got = rr * pmfit.p_of_s(c, rr * rr)
+    want = _fitform(rr)
+    assert np.all(np.abs(got - want) <= 0.04 * want), np.max(np.abs(got / want - 1))
+    res = r * pmfit.p_of_s(c, r * r) - f
+    for lo in (0.5, 1.5, 2.5):
+        sel = (r >= lo) & (r < lo + 0.5)
+        assert abs(res[sel].mean()) <= 4 * res[sel].std() / np.sqrt(sel.sum()) + 1e-3
