@@ -138,13 +138,15 @@ def pm_accel(pos, m, ng: int, L: float, sigma: float = 0.8, ns: int = 3,
 
 
 def ksk_step(pos, vel, m, L: float, ng: int, r_max: float, eps: float, poly, dt: float,
-             nsub: int, a_lr=None, sigma: float = 0.8, ns: int = 3):
+             nsub: int, a_lr=None, sigma: float = 0.8, ns: int = 3, ml=None):
     """One full step of Eq. (tstep): a long-range half kick, nsub short-range
     stream-kick-stream subcycles of length dt / nsub (Sec. 2.5), then the
     long-range force at the new positions and the second half kick.
 
     a_lr, if given, is the PM acceleration at the incoming positions (the
-    previous step's final one); returns (pos, vel, a_lr_new, a_sr_last)."""
+    previous step's final one); ml = (d, l_min, l_max, cell) replaces each
+    subcycle by the multilevel one of oracle.ml (then a_sr_last is None).
+    Returns (pos, vel, a_lr_new, a_sr_last)."""
     pos = np.array(pos, dtype=np.float64)
     vel = np.array(vel, dtype=np.float64)
     m = np.asarray(m, dtype=np.float64)
@@ -154,7 +156,14 @@ def ksk_step(pos, vel, m, L: float, ng: int, r_max: float, eps: float, poly, dt:
     tau = dt / nsub
     a_sr = np.zeros_like(pos)
     for _ in range(nsub):
-        pos, vel, a_sr = _sr.sks(pos, vel, m, L, r_max, eps, poly, tau)
+        if ml is None:
+            pos, vel, a_sr = _sr.sks(pos, vel, m, L, r_max, eps, poly, tau)
+        else:
+            from oracle import ml as _ml
+            d, lmin, lmax, cell = ml
+            pos, vel, _ = _ml.subcycle(pos, vel, m, L, cell, r_max, eps, poly, tau, d, lmin,
+                                       lmax)
+            a_sr = None
     a_lr = pm_accel(pos, m, ng, L, sigma, ns)
     vel = vel + 0.5 * dt * a_lr
     return pos, vel, a_lr, a_sr
