@@ -33,8 +33,8 @@ typedef struct sr_pm sr_pm;
  * to ctx (its device and stream).  ng must be a power of two in [8, 1024];
  * sigma > 0 (grid spacings) and ns >= 0 are the filter parameters of Eq.
  * (filter) (nominal 0.8 and 3).  The solver owns two complex float32 grids
- * (16 ng^3 bytes) and its k-space tables, built in FP64 on the host and
- * uploaded before this call returns.  Errors: SR_EINVAL, SR_ENOMEM,
+ * and a 64-bit deposit grid (24 ng^3 bytes) and its k-space tables, built in
+ * FP64 on the host and uploaded before this call returns.  Errors: SR_EINVAL, SR_ENOMEM,
  * SR_EDEVICE. */
 int sr_pm_create(sr_ctx *ctx, int32_t ng, double len, float sigma, int32_t ns, sr_pm **out);
 
@@ -79,6 +79,15 @@ typedef struct sr_step_params {
     double cell;        /* chaining cell of the split coordinates */
     float dt;           /* full step length */
     int32_t n_sub;      /* short-range subcycles per step (>= 1) */
+    /* Multilevel subcycles (Sec. 3.1, Eq. (kicks)); ml_d = 0: off.  At the
+     * start of each subcycle a particle gets l = floor(rho/rho_0) / ml_d + 1
+     * kicks (integer division; rho/rho_0 = its chaining cell's count over
+     * the mean count), clamped to [ml_min, ml_max] (1 <= ml_min <= ml_max <= 4).
+     * Every particle streams in M = 2 lcm(ml_min..ml_max) pieces of tau/M; a
+     * particle of level l kicks by tau/l after the pieces m with 2 m l / M
+     * odd, with the short-range force evaluated for the cells holding such
+     * particles. */
+    int32_t ml_d, ml_min, ml_max;
 } sr_step_params;
 
 /* One full step of Eq. (tstep) (Sec. 2.5) on resident split state of a
@@ -91,8 +100,10 @@ typedef struct sr_step_params {
  * the PM acceleration: read as the value at the incoming positions when
  * lr_valid != 0 (the previous step's output), else computed first; on return
  * they hold it at the outgoing positions.  sr_ax/ay/az (device float[n])
- * receive the last subcycle's short-range acceleration.  Tuning and scratch
- * come from the context as for sr_force_split.  Errors: SR_EINVAL (box not a
+ * receive the last subcycle's short-range acceleration (multilevel: each
+ * particle's value from the last evaluation that covered its cell).  Tuning
+ * and scratch come from the context as for sr_force_split (multilevel adds
+ * 2 n + 4 n_cells bytes).  Errors: SR_EINVAL (box not a
  * periodic cube of the solver's side, bad parameters), SR_ENOMEM; SR_ERANGE
  * from sr_sync. */
 int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, float *oy, float *oz,

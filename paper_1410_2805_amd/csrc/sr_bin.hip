@@ -393,8 +393,22 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
 #pragma unroll
     for (int k = 0; k <= kSegGroup; ++k)
         bounds[k] = __builtin_amdgcn_readfirstlane(offsets[c0 + (k < nc ? k : nc)]);
-    if (chunk_count && lane < nc)
-        chunk_count[c0 + lane] = chunks_for(offsets[c0 + lane + 1] - offsets[c0 + lane]);
+    if (chunk_count && lane < nc) {
+        const int c = c0 + lane;
+        const int lo = offsets[c], hi = offsets[c + 1];
+        int q = chunks_for(hi - lo);
+        if (q) {
+            // an activity mask drops the cells without an active particle
+            const BoxDesc &d = box_at(B, find_box(B.cstart, B.nb, c));
+            if (d.active) {
+                bool any = false;
+                for (int k = lo; k < hi && !any; ++k)
+                    any = d.active[perm[k] - d.pbase] != 0;
+                q = any ? q : 0;
+            }
+        }
+        chunk_count[c] = q;
+    }
     const int b = bounds[0];
     const int total = bounds[kSegGroup] - b;
     if (total <= 64) {

@@ -831,14 +831,16 @@ static int single_batch(sr_ctx *ctx, const float *x, const float *y, const float
     return SR_OK;
 }
 
-extern "C" int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
-                              const float *oz, const float *mass, int64_t n, const sr_box *box,
-                              double cell, float r_max, float eps, const float poly[6], float *ax,
-                              float *ay, float *az, double *momentum3)
+// sr_force_split with an optional activity mask (cells without an active
+// particle get no work items; their particles' outputs are left as they
+// were).  Also the arena bytes such a call uses (bytes != nullptr: sizing
+// only, nothing is enqueued).
+int force_split_masked(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
+                       const float *oz, const float *mass, int64_t n, const sr_box *box,
+                       double cell, float r_max, float eps, const float poly[6], float *ax,
+                       float *ay, float *az, double *momentum3, const unsigned char *active,
+                       size_t *bytes)
 {
-    if (!ctx)
-        return SR_EINVAL;
-    ctx->err.clear();
     int rc = check_force_params(ctx, r_max, eps, poly);
     if (rc)
         return rc;
@@ -856,11 +858,16 @@ extern "C" int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox
                            kSplitMaxCells);
     B.one.g.split = 1;
     B.one.cell3 = cell3;
-    if (hipSetDevice(ctx->device) != hipSuccess)
-        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    B.one.active = active;
     Bump sz{nullptr, 0, 0};
     ForceScratch s;
     force_layout(sz, n, B.ctot, 1, s);
+    if (bytes) {
+        *bytes = sz.off;
+        return SR_OK;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
     if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
@@ -868,6 +875,18 @@ extern "C" int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox
     const ForceParams fp = make_params(r_max, eps, poly);
     const int rec = sr_timing_begin(ctx);
     return force_enqueue(ctx, B, s, fp, ctx->order, ctx->persistent, momentum3, rec);
+}
+
+extern "C" int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
+                              const float *oz, const float *mass, int64_t n, const sr_box *box,
+                              double cell, float r_max, float eps, const float poly[6], float *ax,
+                              float *ay, float *az, double *momentum3)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    return force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box, cell, r_max, eps, poly, ax,
+                              ay, az, momentum3, nullptr, nullptr);
 }
 
 extern "C" int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force,

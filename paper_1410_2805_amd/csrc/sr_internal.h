@@ -66,6 +66,7 @@ struct BoxDesc {
     int pbase, n, cbase, _pad;
     const float *x, *y, *z, *m;   // positions, or cell offsets when g.split
     const int *cell3;             // split coordinates: packed chaining cells
+    const unsigned char *active;  // optional: only cells holding an active particle get items
     float *ax, *ay, *az;
 };
 
@@ -198,6 +199,11 @@ int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int
                    Geom *g);
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly);
 ForceParams make_params(float r_max, float eps, const float *poly);
+int force_split_masked(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
+                       const float *oz, const float *mass, int64_t n, const sr_box *box,
+                       double cell, float r_max, float eps, const float poly[6], float *ax,
+                       float *ay, float *az, double *momentum3, const unsigned char *active,
+                       size_t *bytes);
 // Enqueue bin + items (+ cost order) + pair loop + momentum for a batch.
 // order: 0 cell order, 1 cost buckets; persistent: one wave per CU slot
 // pulling items from a counter.  mom: device double[3 * nb] or nullptr.

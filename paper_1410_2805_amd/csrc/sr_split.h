@@ -38,3 +38,18 @@ int slot_update_enqueue(sr_ctx *ctx, const SlotState *slots, const int *start, i
 int kick_stream_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
                         float *oz, float *vx, float *vy, float *vz, const float *ax,
                         const float *ay, const float *az, float kick, double stream);
+
+// Multilevel stepping (Sec. 3.1, Eq. (kicks)) on one box of split state.
+// level[i] = clamp(floor(count * ncell / n) / d + 1, lmin, lmax) from the
+// chaining-cell counts (counts: ncell ints of scratch).
+int ml_levels_enqueue(sr_ctx *ctx, const SplitGeom &sg, const int *cell3, int n, int *counts,
+                      int d, int lmin, int lmax, unsigned char *level);
+// active[i] = 1 where level[i] kicks after stream piece m of M.
+int ml_active_enqueue(sr_ctx *ctx, const unsigned char *level, int n, int m, int M,
+                      unsigned char *active);
+// Kick the particles whose level kicks at m by a tau / level (a may be null),
+// then stream every particle by `stream` (0: none).
+int ml_update_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
+                      float *oz, float *vx, float *vy, float *vz, const float *ax,
+                      const float *ay, const float *az, const unsigned char *level, int m, int M,
+                      double tau, double stream);

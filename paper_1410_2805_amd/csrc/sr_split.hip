@@ -190,6 +190,100 @@ __global__ __launch_bounds__(kBlock) void k_kick_stream(SplitGeom sg, int n, int
     cell3[i] = pack3(c);
 }
 
+// ---- multilevel stepping (Sec. 3.1, Eq. (kicks)) --------------------------
+
+__device__ __forceinline__ int split_cell_index(int packed, const SplitGeom &sg)
+{
+    int c[3];
+    unpack3(packed, c);
+    return c[0] + sg.nc[0] * (c[1] + sg.nc[1] * c[2]);
+}
+
+// Particles per chaining cell (counts cleared by the caller).
+__global__ __launch_bounds__(kBlock) void k_ml_count(const int *__restrict__ cell3, int n,
+                                                     SplitGeom sg, int *__restrict__ counts)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        atomicAdd(counts + split_cell_index(cell3[i], sg), 1);
+}
+
+// Kicks per subcycle: l = floor(rho / rho_0) / d + 1 clamped to [lmin, lmax],
+// rho / rho_0 = count * ncell / n (FP64).
+__global__ __launch_bounds__(kBlock) void k_ml_level(const int *__restrict__ cell3, int n,
+                                                     SplitGeom sg, const int *__restrict__ counts,
+                                                     int d, int lmin, int lmax,
+                                                     unsigned char *__restrict__ level)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const double ncell = (double)sg.nc[0] * sg.nc[1] * sg.nc[2];
+    const long long r = (long long)floor((double)counts[split_cell_index(cell3[i], sg)] * ncell /
+                                         (double)n);
+    long long l = r / d + 1;
+    l = l < lmin ? lmin : (l > lmax ? lmax : l);
+    level[i] = (unsigned char)l;
+}
+
+__device__ __forceinline__ bool ml_kicks(int l, int m, int M)
+{
+    const int t = 2 * m * l;
+    return t % M == 0 && ((t / M) & 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ml_active(const unsigned char *__restrict__ level,
+                                                      int n, int m, int M,
+                                                      unsigned char *__restrict__ active)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        active[i] = ml_kicks(level[i], m, M) ? 1 : 0;
+}
+
+// After stream piece m: particles of a level that kicks at m take v += a tau/l
+// (when a is given); then every particle streams o += v * stream.
+__global__ __launch_bounds__(kBlock) void k_ml_update(SplitGeom sg, int n, int *__restrict__ cell3,
+                                                      float *__restrict__ ox,
+                                                      float *__restrict__ oy,
+                                                      float *__restrict__ oz,
+                                                      float *__restrict__ vx,
+                                                      float *__restrict__ vy,
+                                                      float *__restrict__ vz,
+                                                      const float *__restrict__ ax,
+                                                      const float *__restrict__ ay,
+                                                      const float *__restrict__ az,
+                                                      const unsigned char *__restrict__ level,
+                                                      int m, int M, double tau, double stream)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    float v[3] = {vx[i], vy[i], vz[i]};
+    const int l = level[i];
+    if (ax && ml_kicks(l, m, M)) {
+        const float kick = (float)(tau / (double)l);
+        v[0] = fmaf(ax[i], kick, v[0]);
+        v[1] = fmaf(ay[i], kick, v[1]);
+        v[2] = fmaf(az[i], kick, v[2]);
+        vx[i] = v[0];
+        vy[i] = v[1];
+        vz[i] = v[2];
+    }
+    if (stream == 0.0)
+        return;
+    int c[3];
+    unpack3(cell3[i], c);
+    float *o[3] = {ox, oy, oz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double off = (double)o[k][i] + (double)v[k] * stream;
+        rehome(off, c[k], sg.h[k], sg.nc[k]);
+        o[k][i] = (float)off;
+    }
+    cell3[i] = pack3(c);
+}
+
 }  // namespace
 
 int split_geom(sr_ctx *ctx, const sr_box *box, double cell, SplitGeom *sg)
@@ -289,4 +383,43 @@ int kick_stream_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, flo
                        ctx->stream, sg, n, cell3, ox, oy, oz, vx, vy, vz, ax, ay, az, kick,
                        stream);
     return sr_check_launch(ctx, "k_kick_stream");
+}
+
+int ml_levels_enqueue(sr_ctx *ctx, const SplitGeom &sg, const int *cell3, int n, int *counts,
+                      int d, int lmin, int lmax, unsigned char *level)
+{
+    if (n <= 0)
+        return SR_OK;
+    const int64_t ncell = (int64_t)sg.nc[0] * sg.nc[1] * sg.nc[2];
+    int rc = fill_enqueue(ctx, counts, 0, ncell);
+    if (rc)
+        return rc;
+    const dim3 grid((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_ml_count, grid, dim3(kBlock), 0, ctx->stream, cell3, n, sg, counts);
+    hipLaunchKernelGGL(k_ml_level, grid, dim3(kBlock), 0, ctx->stream, cell3, n, sg, counts, d,
+                       lmin, lmax, level);
+    return sr_check_launch(ctx, "k_ml_level");
+}
+
+int ml_active_enqueue(sr_ctx *ctx, const unsigned char *level, int n, int m, int M,
+                      unsigned char *active)
+{
+    if (n <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_ml_active, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, ctx->stream,
+                       level, n, m, M, active);
+    return sr_check_launch(ctx, "k_ml_active");
+}
+
+int ml_update_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
+                      float *oz, float *vx, float *vy, float *vz, const float *ax,
+                      const float *ay, const float *az, const unsigned char *level, int m, int M,
+                      double tau, double stream)
+{
+    if (n <= 0)
+        return SR_OK;
+    hipLaunchKernelGGL(k_ml_update, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, ctx->stream,
+                       sg, n, cell3, ox, oy, oz, vx, vy, vz, ax, ay, az, level, m, M, tau,
+                       stream);
+    return sr_check_launch(ctx, "k_ml_update");
 }

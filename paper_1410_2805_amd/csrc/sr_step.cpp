@@ -1,5 +1,6 @@
 // The full step of Eq. (tstep) (Sec. 2.5): long-range half kicks around
 // n_sub short-range stream-kick-stream subcycles, on resident split state.
+#include <climits>
 #include <cmath>
 
 #include "sr_internal.h"
@@ -36,6 +37,9 @@ extern "C" int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, fl
         return sr_fail(ctx, SR_EINVAL, "NULL pointer with n > 0");
     if (p->n_sub < 1 || !std::isfinite(p->dt))
         return sr_fail(ctx, SR_EINVAL, "n_sub must be >= 1 and dt finite");
+    const bool ml = p->ml_d > 0;
+    if (p->ml_d < 0 || (ml && !(1 <= p->ml_min && p->ml_min <= p->ml_max && p->ml_max <= 4)))
+        return sr_fail(ctx, SR_EINVAL, "multilevel needs ml_d >= 0 and 1 <= ml_min <= ml_max <= 4");
     SplitGeom sg;
     int rc = split_geom(ctx, box, p->cell, &sg);
     if (rc)
@@ -45,12 +49,75 @@ extern "C" int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, fl
     if (hipSetDevice(ctx->device) != hipSuccess)
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
     const int ni = (int)n;
+    // multilevel scratch sits after the force pass's part of the arena
+    unsigned char *level = nullptr, *active = nullptr;
+    int *counts = nullptr;
+    if (ml) {
+        size_t fbytes = 0;
+        if ((rc = force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box, p->cell, p->r_max,
+                                     p->eps, p->poly, sr_ax, sr_ay, sr_az, nullptr, nullptr,
+                                     &fbytes)))
+            return rc;
+        const size_t a = 256;
+        const size_t ncell = (size_t)sg.nc[0] * sg.nc[1] * sg.nc[2];
+        const size_t off_level = (fbytes + a - 1) / a * a;
+        const size_t off_active = off_level + ((size_t)n + a - 1) / a * a;
+        const size_t off_counts = off_active + ((size_t)n + a - 1) / a * a;
+        if ((rc = sr_arena_reserve(ctx, off_counts + ncell * sizeof(int))))
+            return rc;
+        level = reinterpret_cast<unsigned char *>(ctx->arena + off_level);
+        active = reinterpret_cast<unsigned char *>(ctx->arena + off_active);
+        counts = reinterpret_cast<int *>(ctx->arena + off_counts);
+    }
     if (!lr_valid &&
         (rc = pm_force_split_enqueue(pm, cell3, ox, oy, oz, mass, ni, sg.h, lr_ax, lr_ay, lr_az)))
         return rc;
     const double tau = (double)p->dt / p->n_sub;
     const double half_tau = 0.5 * tau;
     const float half_dt = (float)(0.5 * (double)p->dt);
+    if (ml) {
+        int M = 1;
+        for (int l = p->ml_min; l <= p->ml_max; ++l) {
+            int g = M, b = l;
+            while (b) {
+                const int t = g % b;
+                g = b;
+                b = t;
+            }
+            M = M / g * l;
+        }
+        M *= 2;
+        if ((rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, lr_ax, lr_ay,
+                                      lr_az, half_dt, 0.0)))
+            return rc;
+        const double piece = tau / M;
+        for (int c = 0; c < p->n_sub; ++c) {
+            if ((rc = ml_levels_enqueue(ctx, sg, cell3, ni, counts, p->ml_d, p->ml_min, p->ml_max,
+                                        level)) ||
+                (rc = ml_update_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, nullptr,
+                                        nullptr, nullptr, level, 0, M, tau, piece)))
+                return rc;
+            for (int m = 1; m <= M; ++m) {
+                bool any = false;
+                for (int l = p->ml_min; l <= p->ml_max; ++l)
+                    any = any || ((2 * m * l) % M == 0 && ((2 * m * l / M) & 1));
+                if (any && ((rc = ml_active_enqueue(ctx, level, ni, m, M, active)) ||
+                            (rc = force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box,
+                                                     p->cell, p->r_max, p->eps, p->poly, sr_ax,
+                                                     sr_ay, sr_az, nullptr, active, nullptr))))
+                    return rc;
+                if ((rc = ml_update_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz,
+                                            any ? sr_ax : nullptr, sr_ay, sr_az, level, m, M, tau,
+                                            m < M ? piece : 0.0)))
+                    return rc;
+            }
+        }
+        if ((rc = pm_force_split_enqueue(pm, cell3, ox, oy, oz, mass, ni, sg.h, lr_ax, lr_ay,
+                                         lr_az)))
+            return rc;
+        return kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, lr_ax, lr_ay,
+                                   lr_az, half_dt, 0.0);
+    }
     // long-range half kick fused with the first subcycle's first stream
     if ((rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, lr_ax, lr_ay, lr_az,
                                   half_dt, half_tau)))

@@ -91,13 +91,17 @@ class StepParams(ctypes.Structure):
     """sr_step_params: one full step of Eq. (tstep)."""
 
     _fields_ = [("r_max", ctypes.c_float), ("eps", ctypes.c_float), ("poly", ctypes.c_float * 6),
-                ("cell", ctypes.c_double), ("dt", ctypes.c_float), ("n_sub", ctypes.c_int32)]
+                ("cell", ctypes.c_double), ("dt", ctypes.c_float), ("n_sub", ctypes.c_int32),
+                ("ml_d", ctypes.c_int32), ("ml_min", ctypes.c_int32), ("ml_max", ctypes.c_int32)]
 
     @staticmethod
-    def make(r_max, eps, poly, cell, dt, n_sub) -> "StepParams":
+    def make(r_max, eps, poly, cell, dt, n_sub, ml=None) -> "StepParams":
+        """ml = (d, l_min, l_max) switches on multilevel subcycles."""
         p = StepParams()
         p.r_max, p.eps, p.cell, p.dt, p.n_sub = float(r_max), float(eps), float(cell), float(dt), \
             int(n_sub)
+        if ml is not None:
+            p.ml_d, p.ml_min, p.ml_max = (int(v) for v in ml)
         for k in range(6):
             p.poly[k] = float(poly[k])
         return p
