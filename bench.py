@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="zeldovich128",
-                    choices=sorted(WORKLOADS) + ["batch64", "serving", "ksk128"])
+                    choices=sorted(WORKLOADS) + ["batch64", "serving", "ksk128", "ksk_ml128"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
     ap.add_argument("--replays", type=int, default=200, help="batch64: timed graph replays")
     ap.add_argument("--cell", type=float, default=3.0)
@@ -130,6 +130,8 @@ def main():
         return bench_serving(args)
     if args.workload == "ksk128":
         return bench_step(args)
+    if args.workload == "ksk_ml128":
+        return bench_step_ml(args)
     dev = torch.device("cuda:0")
     if args.calib_copy:
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -453,6 +455,117 @@ def bench_step(args):
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    pm.close()
+    ctx.close()
+
+
+def bench_step_ml(args):
+    """Multilevel subcycles (Sec. 3.1, Eq. (kicks)) against plain subcycles.
+    Each variant times single full steps, every one from the same saved
+    state, so that both cost the same configuration.  Plain: n_sub = 3 (three
+    short-range kicks for every particle); multilevel: one subcycle with
+    1..3 kicks by density.  Two boxes of 128^3 particles, L = 128, PM 128^3:
+    a mildly nonlinear Zel'dovich box (rms displacement 4 cells, growing-mode
+    velocities, d = 5), where sparse particles carry most of the pair work,
+    and a halo-dominated box (70 % NFW halos, at rest, d = 20), where the
+    densest particles do."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2805_amd import gridfit, sr, workloads
+
+    dev = torch.device("cuda:0")
+    ng, L, cell, dt = 128, 128.0, 3.0, 0.002
+    poly = gridfit.poly_coeffs()
+    box = sr.Box.make(L)
+    n = 128 ** 3
+    ctx = sr.Context(0, arena_bytes=sr.sr_scratch_bytes(box, cell, n, True) + 3 * n + 2 ** 22)
+    pm = sr.PM(ctx, ng, L)
+    reps = max(2, min(args.steps, 8))
+
+    def levels_of(pos, d):
+        nc = int(L // cell)
+        idx = np.minimum((pos // (L / nc)).astype(np.int64), nc - 1)
+        lin = idx[:, 0] + nc * (idx[:, 1] + nc * idx[:, 2])
+        cnt = np.bincount(lin, minlength=nc ** 3)
+        lev = np.clip(np.floor(cnt[lin] * nc ** 3 / n).astype(np.int64) // d + 1, 1, 3)
+        return np.bincount(lev, minlength=4)[1:].tolist()
+
+    def measure(pos, vel, d):
+        x, y, z = [torch.from_numpy(np.ascontiguousarray(pos[:, k])).to(dev) for k in range(3)]
+        c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+        del x, y, z
+        init = {"cell3": c3, "ox": ox, "oy": oy, "oz": oz,
+                "vx": torch.from_numpy(vel[:, 0].copy()).to(dev),
+                "vy": torch.from_numpy(vel[:, 1].copy()).to(dev),
+                "vz": torch.from_numpy(vel[:, 2].copy()).to(dev)}
+        m = torch.ones(n, device=dev)
+        lr0 = pm.force_split(c3, ox, oy, oz, m, cell)
+        lr0 = tuple(t.clone() for t in lr0)
+        st = {k: v.clone() for k, v in init.items()}
+        st["m"] = m
+        lr = tuple(t.clone() for t in lr0)
+        so = tuple(torch.zeros(n, device=dev) for _ in range(3))
+        out = {}
+        for name, prm in (("plain", sr.StepParams.make(R_MAX, EPS, poly, cell, dt, 3)),
+                          ("multilevel", sr.StepParams.make(R_MAX, EPS, poly, cell, dt, 1,
+                                                            ml=(d, 1, 3)))):
+            times = []
+            for r in range(reps + 1):
+                for k, v in init.items():
+                    st[k].copy_(v)
+                for a, b in zip(lr, lr0):
+                    a.copy_(b)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                sr.sr_ksk_step(ctx, pm, st, box, prm, lr, True, so)
+                e1.record()
+                torch.cuda.synchronize()
+                ctx.sync()
+                if r:
+                    times.append(e0.elapsed_time(e1))
+            out[name] = float(np.median(times))
+        return out
+
+    log("generating the Zel'dovich box (rms displacement 4 cells)")
+    pos = workloads.zeldovich_pos64(128, L, 2, rms=4.0)
+    q = (np.stack(np.meshgrid(*(np.arange(128),) * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5)
+    psi = pos - q
+    psi -= L * np.round(psi / L)
+    vel = (np.sqrt(4.0 * np.pi) * psi).astype(np.float32)
+    del q, psi
+    zel = measure(pos, vel, 5)
+    zel_lev = levels_of(pos, 5)
+    log("zeldovich rms 4: plain %.3f ms, multilevel %.3f ms, levels %s"
+        % (zel["plain"], zel["multilevel"], zel_lev))
+    log("generating the halo-dominated box")
+    p = workloads.nfw_share(n, L, 5, periodic=True)
+    pos = p.pos64()
+    halo = measure(pos, np.zeros((n, 3), np.float32), 20)
+    halo_lev = levels_of(pos, 20)
+    log("halos: plain %.3f ms, multilevel %.3f ms, levels %s"
+        % (halo["plain"], halo["multilevel"], halo_lev))
+    res = {
+        "metric": "multilevel full step (Eq. tstep + Eq. kicks) particle updates/s",
+        "value": n / (zel["multilevel"] * 1e-3), "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": zel["multilevel"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "128^3 Zel'dovich box, rms displacement 4 cells, growing-mode "
+                               "velocities, L=128, PM 128^3, dt=0.002, r_max=3, eps=0.1, cell 3; "
+                               "multilevel d=5, 1..3 kicks in one subcycle vs plain n_sub=3; "
+                               "single steps from one saved state (median)",
+                   "zeldovich_plain_ms": zel["plain"], "zeldovich_multilevel_ms": zel["multilevel"],
+                   "zeldovich_speedup": zel["plain"] / zel["multilevel"],
+                   "zeldovich_particles_per_level": zel_lev,
+                   "halo_box": "128^3, 70% NFW halos at rest, d=20",
+                   "halo_plain_ms": halo["plain"], "halo_multilevel_ms": halo["multilevel"],
+                   "halo_speedup": halo["plain"] / halo["multilevel"],
+                   "halo_particles_per_level": halo_lev},
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(res), flush=True)
     pm.close()

@@ -323,6 +323,19 @@ __global__ __launch_bounds__(kBlock) void k_gather(Batch B, const int *__restric
         atomicOr(&mass_mixed[box], 1);
 }
 
+// Activity mask: flag[cell] = 1 for every cell holding an active particle
+// (the flags were cleared; equal plain stores need no atomics).
+__global__ __launch_bounds__(kBlock) void k_cell_active(Batch B, const int *__restrict__ cid,
+                                                        int *__restrict__ flag)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= B.ntot)
+        return;
+    const BoxDesc &d = box_at(B, find_box(B.pstart, B.nb, i));
+    if (!d.active || d.active[i - d.pbase])
+        flag[cid[i]] = 1;
+}
+
 constexpr int kSegGroup = 4;  // consecutive cells per wavefront
 
 // Sorts one cell's slots [b, b + len) by one wavefront (len <= kLargeCell;
@@ -397,16 +410,10 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
         const int c = c0 + lane;
         const int lo = offsets[c], hi = offsets[c + 1];
         int q = chunks_for(hi - lo);
-        if (q) {
-            // an activity mask drops the cells without an active particle
-            const BoxDesc &d = box_at(B, find_box(B.cstart, B.nb, c));
-            if (d.active) {
-                bool any = false;
-                for (int k = lo; k < hi && !any; ++k)
-                    any = d.active[perm[k] - d.pbase] != 0;
-                q = any ? q : 0;
-            }
-        }
+        // an activity mask drops the cells without an active particle
+        // (k_cell_active left 1 in chunk_count for the others)
+        if (q && box_at(B, find_box(B.cstart, B.nb, c)).active)
+            q = chunk_count[c] ? q : 0;
         chunk_count[c] = q;
     }
     const int b = bounds[0];
@@ -626,6 +633,18 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
                            ctx->stream, B, s.cid, s.slot, s.count, ctx->status);
         if ((rc = sr_check_launch(ctx, "k_cellid")))
             return rc;
+    }
+    // only single-box passes carry an activity mask (the batched forms pass none)
+    const bool masked = !B.boxes && B.one.active != nullptr;
+    if (masked && chunk_count) {
+        if ((rc = fill_enqueue(ctx, chunk_count, 0, B.ctot)))
+            return rc;
+        if (n > 0) {
+            hipLaunchKernelGGL(k_cell_active, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0,
+                               ctx->stream, B, s.cid, chunk_count);
+            if ((rc = sr_check_launch(ctx, "k_cell_active")))
+                return rc;
+        }
     }
     if ((rc = scan_enqueue(ctx, s.count, B.ctot, s.scan_part, offsets, s.scan_flag)))
         return rc;
