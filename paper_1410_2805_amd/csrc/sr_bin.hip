@@ -319,8 +319,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(Batch B, const int *__restric
         sorted[inv[i]] = q;
         mixed = q.w != d.m[0];
     }
-    if (mixed)
-        atomicOr(&mass_mixed[box], 1);
+    // one atomic per wavefront for the lanes that share the lowest flagged
+    // lane's box (all of them in a single-box pass), one per lane otherwise
+    const unsigned long long flagged = __ballot(mixed);
+    if (flagged) {
+        const int first = __ffsll((long long)flagged) - 1;
+        const int b0 = __shfl(box, first);
+        const int lane = threadIdx.x & 63;
+        if (mixed && (box != b0 || lane == first))
+            atomicOr(&mass_mixed[box], 1);
+    }
 }
 
 // Activity mask: flag[cell] = 1 for every cell holding an active particle
