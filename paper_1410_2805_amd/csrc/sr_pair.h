@@ -1,0 +1,227 @@
+// Pair-loop building blocks shared by the chaining-mesh pass (sr_force.hip)
+// and the RCB-tree pass (sr_tree.hip): source pieces, their LDS staging and
+// the float32 pair arithmetic of Eq. (force).
+#pragma once
+
+#include "sr_internal.h"
+
+namespace {
+
+constexpr int kTile = 256;       // sources per LDS tile (4 KiB)
+constexpr float kFar = 1.0e6f;   // padding source far outside any box, mass 0
+
+// Source pieces of one target cell: at most 18 (9 rows, each split where it
+// wraps) in global coordinates, at most 63 (one per cell) in split
+// coordinates.  pbeg[npiece] = all sources; unused pieces are empty.
+constexpr int kMaxPieces = 64;
+struct Stencil {
+    int pbeg[kMaxPieces + 1];  // prefix of piece lengths
+    int psrc[kMaxPieces];      // first sorted slot of each piece
+    float4 psh[kMaxPieces];    // shift added to the piece's coordinates
+};
+
+__device__ __forceinline__ int wave_exclusive_scan(int v, int lane, int *total)
+{
+    int inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(inc, d, 64);
+        if (lane >= d)
+            inc += t;
+    }
+    *total = __shfl(inc, 63, 64);
+    return inc - v;
+}
+
+// Builds the source pieces of target cell (cx, cy, cz) into st (all lanes
+// call).  Global coordinates: lanes < 18 each own one piece slot, row r =
+// lane/2, half = lane%2, the shift is the periodic image shift.  Split
+// coordinates: lanes < 9 (2 hx + 1) each own one cell of the stencil and the
+// shift is the cell's offset from the target cell, (dx w0, dy w1, dz w2), so
+// coordinates stay cell-relative and periodic wrap needs no shift at all.
+__device__ void build_stencil(Stencil &st, const int *__restrict__ offsets, const Geom &g, int cx,
+                              int cy, int cz, const float F[3], int lane)
+{
+    int len = 0, src = 0;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    const int W = 2 * g.hx + 1;
+    if (g.split && lane < 9 * W) {
+        const int r = lane / W, k = lane - r * W;
+        const int dx = k - g.hx, dy = r % 3 - 1, dz = r / 3 - 1;
+        int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+        nx = nx < 0 ? nx + g.nc[0] : (nx >= g.nc[0] ? nx - g.nc[0] : nx);
+        ny = ny < 0 ? ny + g.nc[1] : (ny >= g.nc[1] ? ny - g.nc[1] : ny);
+        nz = nz < 0 ? nz + g.nc[2] : (nz >= g.nc[2] ? nz - g.nc[2] : nz);
+        const int id = nx + g.nc[0] * (ny + g.nc[1] * nz);
+        src = offsets[id];
+        len = offsets[id + 1] - src;
+        sx = (float)((double)dx * g.w[0]);
+        sy = (float)((double)dy * g.w[1]);
+        sz = (float)((double)dz * g.w[2]);
+    } else if (!g.split && lane < 18) {
+        const int r = lane >> 1, half = lane & 1;
+        const int dy = r % 3 - 1, dz = r / 3 - 1;
+        int ny = cy + dy, nz = cz + dz;
+        float shy = F[1], shz = F[2];
+        bool ok = true;
+        if (g.periodic) {
+            if (ny < 0) { ny += g.nc[1]; shy -= g.lenf[1]; }
+            else if (ny >= g.nc[1]) { ny -= g.nc[1]; shy += g.lenf[1]; }
+            if (nz < 0) { nz += g.nc[2]; shz -= g.lenf[2]; }
+            else if (nz >= g.nc[2]) { nz -= g.nc[2]; shz += g.lenf[2]; }
+        } else {
+            ok = ny >= 0 && ny < g.nc[1] && nz >= 0 && nz < g.nc[2];
+        }
+        int x0 = 0, x1 = -1;
+        float shx = F[0];
+        const int n0 = g.nc[0];
+        const int lo = cx - g.hx, hi = cx + g.hx;
+        if (ok) {
+            if (g.periodic) {
+                if (lo < 0) {
+                    if (half == 0) { x0 = 0; x1 = hi; }
+                    else { x0 = lo + n0; x1 = n0 - 1; shx -= g.lenf[0]; }
+                } else if (hi >= n0) {
+                    if (half == 0) { x0 = lo; x1 = n0 - 1; }
+                    else { x0 = 0; x1 = hi - n0; shx += g.lenf[0]; }
+                } else if (half == 0) {
+                    x0 = lo;
+                    x1 = hi;
+                }
+            } else if (half == 0) {
+                x0 = lo > 0 ? lo : 0;
+                x1 = hi < n0 - 1 ? hi : n0 - 1;
+            }
+        }
+        if (x1 >= x0) {
+            const int row = n0 * (ny + g.nc[1] * nz);
+            src = offsets[row + x0];
+            len = offsets[row + x1 + 1] - src;
+        }
+        sx = shx;
+        sy = shy;
+        sz = shz;
+    }
+    int total;
+    int beg = wave_exclusive_scan(len, lane, &total);
+    st.pbeg[lane] = beg;
+    st.psrc[lane] = src;
+    st.psh[lane] = make_float4(sx, sy, sz, 0.f);
+    if (lane == 0)
+        st.pbeg[kMaxPieces] = total;
+}
+
+// A target whose stencil wraps past the upper face of an axis works in a
+// frame shifted by -L along it: its coordinate and the unwrapped sources are
+// all >= L/2 there, so subtracting L is exact, and the wrapped sources need
+// no shift at all.
+__device__ __forceinline__ void frame_shift(const Geom &g, const int cc[3], float F[3])
+{
+    const int h[3] = {g.hx, 1, 1};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        F[d] = (g.periodic && !g.split && cc[d] + h[d] >= g.nc[d]) ? -g.lenf[d] : 0.f;
+}
+
+__device__ __forceinline__ void decode_cell(int cell, const Geom &g, int &cx, int &cy, int &cz)
+{
+    const int plane = g.nc[0] * g.nc[1];
+    cz = cell / plane;
+    const int rem = cell - cz * plane;
+    cy = rem / g.nc[0];
+    cx = rem - cy * g.nc[0];
+}
+
+__device__ __forceinline__ bool is_passive(float4 p, const Geom &g)
+{
+    if (g.periodic)
+        return false;
+    const double c[3] = {(double)p.x, (double)p.y, (double)p.z};
+    bool pas = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        pas = pas || (c[d] < g.skin) || (g.len[d] - c[d] < g.skin);
+    return pas;
+}
+
+// Stage sources [g0, g0 + cntp) of the stencil into the tile.
+__device__ __forceinline__ void stage_tile(float4 *tile, const Stencil &st,
+                                           const float4 *__restrict__ sorted, int g0, int cnt,
+                                           int cntp, int lane, int &p)
+{
+    for (int q = lane; q < cntp; q += 64) {
+        float4 v = make_float4(kFar, kFar, kFar, 0.f);
+        if (q < cnt) {
+            const int gi = g0 + q;
+            while (gi >= st.pbeg[p + 1])
+                ++p;
+            const float4 s = sorted[st.psrc[p] + (gi - st.pbeg[p])];
+            const float4 sh = st.psh[p];
+            v = make_float4(s.x + sh.x, s.y + sh.y, s.z + sh.z, s.w);
+        }
+        tile[q] = v;
+    }
+}
+
+// Loads sources [g0, g0 + cnt) of the stencil (cnt <= kTile) into registers,
+// entry q = lane + 64 k in pre[k]; entries past cnt are far, massless padding.
+__device__ __forceinline__ void load_tile(float4 (&pre)[kTile / 64], const Stencil &st,
+                                          const float4 *__restrict__ sorted, int g0, int cnt,
+                                          int lane, int &p)
+{
+#pragma unroll
+    for (int k = 0; k < kTile / 64; ++k) {
+        const int q = lane + 64 * k;
+        float4 v = make_float4(kFar, kFar, kFar, 0.f);
+        if (q < cnt) {
+            const int gi = g0 + q;
+            while (gi >= st.pbeg[p + 1])
+                ++p;
+            const float4 s = sorted[st.psrc[p] + (gi - st.pbeg[p])];
+            const float4 sh = st.psh[p];
+            v = make_float4(s.x + sh.x, s.y + sh.y, s.z + sh.z, s.w);
+        }
+        pre[k] = v;
+    }
+}
+
+// One tile of pair interactions for one lane: sources src[0 .. cnt) (cnt a
+// multiple of 4), target (xi, yi, zi); partial sums into tx, ty, tz.
+template <bool kUniformMass>
+__device__ __forceinline__ void pair_tile(const float4 *src, int cnt, float xi, float yi, float zi,
+                                          const ForceParams &fp, float &tx, float &ty, float &tz)
+{
+    const float eps = fp.eps, rcut = fp.rcut, q0 = fp.q0;
+    const float n1 = fp.nq[1], n2 = fp.nq[2], n3 = fp.nq[3], n4 = fp.nq[4], n5 = fp.nq[5];
+    for (int j = 0; j < cnt; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float4 s = src[j + u];
+            const float dx = s.x - xi;
+            const float dy = s.y - yi;
+            const float dz = s.z - zi;
+            // se = s + eps; f = se^(-3/2) - q(se) with q(se) = p(se - eps)
+            const float se = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+            const float rs = __builtin_amdgcn_rsqf(se);
+            const float rs2 = rs * rs;
+            const float tt = fmaf(rs2, rs, -q0);
+            float h = fmaf(n5, se, n4);
+            h = fmaf(h, se, n3);
+            h = fmaf(h, se, n2);
+            h = fmaf(h, se, n1);
+            float f = fmaf(h, se, tt);
+            f = se < rcut ? f : 0.f;  // cutoff by select: also zeroes padding
+            if (!kUniformMass)
+                f *= s.w;
+            tx = fmaf(f, dx, tx);
+            ty = fmaf(f, dy, ty);
+            tz = fmaf(f, dz, tz);
+        }
+    }
+}
+
+// Item layout: {cell (global), first sorted slot, targets, S | box << 5}.
+__device__ __forceinline__ int item_split(const int4 &it) { return it.w & 31; }
+__device__ __forceinline__ int item_box(const int4 &it) { return it.w >> 5; }
+
+}  // namespace
