@@ -220,6 +220,32 @@ int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox, const flo
                    float r_max, float eps, const float poly[6], float *ax, float *ay, float *az,
                    double *momentum3);
 
+/* ---- RCB-tree variant (Sec. 2.4 RCB tree, Sec. 3.1 trees per fixed bin) - */
+
+/* sr_force computed with an RCB tree inside every chaining cell instead of
+ * whole-cell stencils.  A cell holding more than leaf_max particles is split
+ * recursively by the plane through the centre of mass of a node (FP64,
+ * mass-weighted) perpendicular to the longest side of its bounding box,
+ * down to leaves of at most leaf_max particles (a node whose box is a point,
+ * whose plane leaves a side empty, or 32 levels deep is a leaf whatever its
+ * size).  Each leaf's particles share one interaction list: the leaves of
+ * the 27 neighbouring cells whose bounding boxes come within r_max of the
+ * leaf's box.  The sum is the same as sr_force's (every pair with
+ * s < r_max^2), in a different order.  Arguments as sr_force, plus
+ * leaf_max (1 .. 2^20); x sub-cells are not used.  Errors as sr_force. */
+int sr_force_tree(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
+                  int64_t n, const sr_box *box, double cell, float r_max, float eps,
+                  const float poly[6], int32_t leaf_max, float *ax, float *ay, float *az,
+                  double *momentum3);
+
+/* The leaves sr_force_tree would use: leaf_of (device int32[n]) receives
+ * the leaf index of every particle (leaves numbered cell by cell); the leaf
+ * count is returned in *n_leaves (HOST; this call waits).  cell >= the
+ * cutoff the caller will use. */
+int sr_tree_leaves(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
+                   int64_t n, const sr_box *box, double cell, int32_t leaf_max, int32_t *leaf_of,
+                   int64_t *n_leaves);
+
 /* ---- Batched form: many independent boxes per pass -------------------- */
 
 /* One box of a batch: device float32 inputs and outputs of its own, its own

@@ -13,7 +13,9 @@ Readings: the centre of mass is mass-weighted, in FP64 (the geometric mean
 when the node's mass is zero); the sides are taken in FP64 from the float32
 bounding box and ties go to the lowest axis; a particle goes to the lower
 child when its coordinate is strictly below the plane; a node whose bounding
-box is a point, or that sits 32 levels deep, is a leaf whatever its size.
+box is a point, whose plane leaves one side empty (possible only with
+massless particles), or that sits 32 levels deep, is a leaf whatever its
+size.
 """
 from __future__ import annotations
 
@@ -38,6 +40,9 @@ def _split(idx, pos, m, leaf_max, depth, out):
     mt = w.sum()
     com = (w * p[:, ax]).sum() / mt if mt > 0 else p[:, ax].mean()
     low = p[:, ax] < com
+    if low.all() or not low.any():     # the plane leaves one side empty
+        out.append(idx)
+        return
     _split(idx[low], pos, m, leaf_max, depth + 1, out)
     _split(idx[~low], pos, m, leaf_max, depth + 1, out)
 

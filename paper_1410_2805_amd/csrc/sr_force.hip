@@ -589,8 +589,16 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
     return SR_OK;
 }
 
+int momentum_enqueue(sr_ctx *ctx, const Batch &B, double *part, double *mom)
+{
+    hipLaunchKernelGGL(k_momentum_partial, dim3(kRedBlocks, B.nb), dim3(256), 0, ctx->stream, B,
+                       part);
+    hipLaunchKernelGGL(k_momentum_final, dim3(B.nb), dim3(256), 0, ctx->stream, part, mom);
+    return sr_check_launch(ctx, "k_momentum");
+}
+
 // Batch of one box, by value.
-static int single_batch(sr_ctx *ctx, const float *x, const float *y, const float *z,
+int single_batch(sr_ctx *ctx, const float *x, const float *y, const float *z,
                         const float *mass, int64_t n, const sr_box *box, double cell, float r_max,
                         int xsplit, float *ax, float *ay, float *az, Batch *B)
 {

@@ -199,6 +199,10 @@ int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int
                    Geom *g);
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly);
 ForceParams make_params(float r_max, float eps, const float *poly);
+int single_batch(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
+                 int64_t n, const sr_box *box, double cell, float r_max, int xsplit, float *ax,
+                 float *ay, float *az, Batch *B);
+int momentum_enqueue(sr_ctx *ctx, const Batch &B, double *part, double *mom);
 int force_split_masked(sr_ctx *ctx, const int32_t *cell3, const float *ox, const float *oy,
                        const float *oz, const float *mass, int64_t n, const sr_box *box,
                        double cell, float r_max, float eps, const float poly[6], float *ax,

@@ -154,6 +154,10 @@ def _load():
         "sr_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "sr_timing_collect": (ctypes.c_int, [P, ctypes.POINTER(f64), ctypes.POINTER(f64),
                                              ctypes.POINTER(i64)]),
+        "sr_force_tree": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, f32, f32, P, i32, P, P, P,
+                                         P]),
+        "sr_tree_leaves": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, i32, P,
+                                          ctypes.POINTER(i64)]),
         "sr_pm_create": (ctypes.c_int, [P, i32, f64, f32, i32, ctypes.POINTER(P)]),
         "sr_pm_destroy": (ctypes.c_int, [P]),
         "sr_pm_bytes": (ctypes.c_int, [i32, ctypes.POINTER(sz)]),
@@ -184,7 +188,8 @@ def exported_symbols() -> list[str]:
             "sr_server_create", "sr_server_submit", "sr_server_tick", "sr_server_poll",
             "sr_server_cancel", "sr_server_info_get", "sr_server_destroy",
             "sr_pm_create", "sr_pm_destroy", "sr_pm_bytes", "sr_pm_deposit", "sr_pm_fft",
-            "sr_pm_force", "sr_pm_force_split", "sr_ksk_step"]
+            "sr_pm_force", "sr_pm_force_split", "sr_ksk_step", "sr_force_tree",
+            "sr_tree_leaves"]
 
 
 def _ptr(t):
@@ -378,6 +383,37 @@ def sr_force_split(ctx: Context, cell3, ox, oy, oz, m, box: Box, cell: float, r_
                                   float(r_max), float(eps), c, _f32(ax, n, "ax"),
                                   _f32(ay, n, "ay"), _f32(az, n, "az"), _ptr(mom)))
     return ax, ay, az, mom
+
+
+def sr_force_tree(ctx: Context, x, y, z, m, box: Box, cell: float, r_max: float, eps: float,
+                  poly, leaf_max: int = 128, out=None, momentum: bool = False):
+    """sr_force through RCB trees in the chaining cells (include/sr.h)."""
+    n = int(x.shape[0])
+    dev = x.device
+    if out is None:
+        out = tuple(torch.empty(max(n, 1), dtype=torch.float32, device=dev)[:n] for _ in range(3))
+    ax, ay, az = out
+    mom = torch.zeros(3, dtype=torch.float64, device=dev) if momentum else None
+    c = (ctypes.c_float * 6)(*[float(v) for v in poly])
+    ctx._bind_stream()
+    ctx._check(lib.sr_force_tree(ctx._h, _f32(x, n, "x"), _f32(y, n, "y"), _f32(z, n, "z"),
+                                 _f32(m, n, "mass"), n, ctypes.byref(box), float(cell),
+                                 float(r_max), float(eps), c, int(leaf_max), _f32(ax, n, "ax"),
+                                 _f32(ay, n, "ay"), _f32(az, n, "az"), _ptr(mom)))
+    return ax, ay, az, mom
+
+
+def sr_tree_leaves(ctx: Context, x, y, z, m, box: Box, cell: float, leaf_max: int = 128):
+    """(leaf index of every particle as an int32 device tensor, leaf count);
+    waits."""
+    n = int(x.shape[0])
+    leaf_of = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)[:n]
+    cnt = ctypes.c_int64()
+    ctx._bind_stream()
+    ctx._check(lib.sr_tree_leaves(ctx._h, _f32(x, n, "x"), _f32(y, n, "y"), _f32(z, n, "z"),
+                                  _f32(m, n, "mass"), n, ctypes.byref(box), float(cell),
+                                  int(leaf_max), _ptr(leaf_of), ctypes.byref(cnt)))
+    return leaf_of, int(cnt.value)
 
 
 def sr_pair_stats(ctx: Context, x, y, z, box: Box, cell: float, r_max: float,
