@@ -100,7 +100,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="zeldovich128",
-                    choices=sorted(WORKLOADS) + ["batch64", "serving", "ksk128", "ksk_ml128"])
+                    choices=sorted(WORKLOADS) + ["batch64", "serving", "ksk128", "ksk_ml128",
+                                                 "tree"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
     ap.add_argument("--replays", type=int, default=200, help="batch64: timed graph replays")
     ap.add_argument("--cell", type=float, default=3.0)
@@ -132,6 +133,8 @@ def main():
         return bench_step(args)
     if args.workload == "ksk_ml128":
         return bench_step_ml(args)
+    if args.workload == "tree":
+        return bench_tree(args)
     dev = torch.device("cuda:0")
     if args.calib_copy:
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -570,6 +573,75 @@ def bench_step_ml(args):
     print(json.dumps(res), flush=True)
     pm.close()
     ctx.close()
+
+
+def bench_tree(args):
+    """The RCB-tree short-range pass (sr_force_tree) next to the chaining-mesh
+    pass (sr_force) on the same inputs: zeldovich128 and nfw256, leaf sizes
+    32 .. 512.  Times whole calls (binning, tree build, leaf tables, pair
+    loop, write-back) with HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2805_amd import gridfit, sr, workloads
+
+    dev = torch.device("cuda:0")
+    poly = gridfit.poly_coeffs()
+    out = {}
+    for name in ("zeldovich128", "nfw256"):
+        p = workloads.config(name)
+        t = {k: torch.from_numpy(getattr(p, k)).to(dev) for k in "xyzm"}
+        box = sr.Box.make(p.L, periodic=p.periodic, skin=p.skin)
+        ctx = sr.Context(0)
+        acc = tuple(torch.empty(p.n, device=dev) for _ in range(3))
+        useful, _, _ = sr.sr_pair_stats(ctx, t["x"], t["y"], t["z"], box, 3.0, R_MAX)
+        reps = 10 if name == "zeldovich128" else 3
+
+        def timed(fn):
+            fn()
+            ctx.sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ctx.sync()
+            return e0.elapsed_time(e1) / reps
+
+        res = {"n": p.n, "useful_pairs": useful}
+        res["mesh_ms"] = timed(lambda: sr.sr_force(ctx, t["x"], t["y"], t["z"], t["m"], box, 3.0,
+                                                   R_MAX, EPS, poly, out=acc))
+        for lm in (32, 128, 512):
+            ctx.timing_enable(True)
+            ctx.timing_collect()
+            ms = timed(lambda: sr.sr_force_tree(ctx, t["x"], t["y"], t["z"], t["m"], box, 3.0,
+                                                R_MAX, EPS, poly, leaf_max=lm, out=acc))
+            prep, pair, calls = ctx.timing_collect()
+            ctx.timing_enable(False)
+            _, nleaves = sr.sr_tree_leaves(ctx, t["x"], t["y"], t["z"], t["m"], box, 3.0, lm)
+            res["tree_%d" % lm] = {"ms": ms, "prep_ms": prep / max(calls, 1),
+                                   "pair_loop_ms": pair / max(calls, 1), "leaves": nleaves}
+            log("%s leaf_max %d: tree %.3f ms (prep %.3f, pair loop %.3f), mesh %.3f ms"
+                % (name, lm, ms, prep / max(calls, 1), pair / max(calls, 1), res["mesh_ms"]))
+        out[name] = res
+        ctx.close()
+    best = min((v["ms"], k) for k, v in out["nfw256"].items() if k.startswith("tree_"))
+    res = {
+        "metric": "RCB-tree short-range pair interactions/s (nfw256)",
+        "value": out["nfw256"]["useful_pairs"] / (best[0] * 1e-3),
+        "unit": "useful directed pair interactions/s",
+        "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": best[0],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "nfw256 and zeldovich128 (see the default bench), "
+                               "r_max=3, eps=0.1, cell 3; tree leaf sizes 32, 128, 512 "
+                               "against the chaining-mesh pass", "best": best[1],
+                   "results": out},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def bench_serving(args):
