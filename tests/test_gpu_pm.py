@@ -327,3 +327,46 @@ def test_ksk_step_rejects_mismatched_box(sr, ctx):
                            (z(), z(), z()))
     finally:
         pmh.close()
+
+
+@pytest.mark.slow
+def test_ksk_step_full_size(sr, ctx):
+    """One full step on the 128^3 box as the step bench runs it (n_sub = 1
+    here): the returned short-range acceleration, which acts at the
+    positions after the long-range half kick and the first half stream, on
+    sampled particles against the FP64 oracles; and total momentum kept to
+    float32 rounding over the whole box."""
+    from tests.parity import check_accel as check_sr
+    L, ng, cell, dt = 128.0, 128, 3.0, 0.002
+    pos = W.zeldovich_pos64(128, L, 2)
+    n = pos.shape[0]
+    q = (np.stack(np.meshgrid(*(np.arange(128),) * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5)
+    psi = pos - q
+    psi -= L * np.round(psi / L)
+    vel = (np.sqrt(4.0 * np.pi) * psi).astype(np.float32)
+    m = np.ones(n, np.float32)
+    poly = gridfit.poly_coeffs()
+    box = sr.Box.make(L)
+    x, y, z = [_dev(pos[:, d], torch.float64) for d in range(3)]
+    c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
+    st = {"cell3": c3, "ox": ox, "oy": oy, "oz": oz, "vx": _dev(vel[:, 0]), "vy": _dev(vel[:, 1]),
+          "vz": _dev(vel[:, 2]), "m": _dev(m)}
+    lr = tuple(torch.zeros(n, dtype=torch.float32, device="cuda:0") for _ in range(3))
+    so = tuple(torch.zeros(n, dtype=torch.float32, device="cuda:0") for _ in range(3))
+    pmh = sr.PM(ctx, ng, L)
+    try:
+        sr.sr_ksk_step(ctx, pmh, st, box, sr.StepParams.make(R_MAX, EPS, poly, cell, dt, 1), lr,
+                       0, so)
+        ctx.sync()
+    finally:
+        pmh.close()
+    v1 = _np(st["vx"], st["vy"], st["vz"])
+    dv = v1 - vel.astype(np.float64)
+    assert np.abs(dv.sum(0)).max() <= 1e-5 * np.abs(dv).sum()
+    # positions where the short-range force acted: x0 + (v0 + a_lr(x0) dt/2) dt/2
+    a_lr0 = PMO.pm_accel(pos, m.astype(np.float64), ng, L)
+    xh = np.mod(pos + (vel.astype(np.float64) + 0.5 * dt * a_lr0) * (0.5 * dt), L)
+    tg = np.sort(np.random.default_rng(31).choice(n, 1024, replace=False))
+    ref = O.force(xh[:, 0], xh[:, 1], xh[:, 2], m, L, R_MAX, EPS, poly.astype(np.float64),
+                  targets=tg)
+    check_sr(_np(*so)[tg], ref, "step a_sr at 128^3")

@@ -117,3 +117,37 @@ def test_tree_empty_and_bad_arguments(sr, ctx, poly):
         with pytest.raises(sr.SRError):
             sr.sr_force_tree(ctx, t["x"], t["y"], t["z"], t["m"], sr.Box.make(12.0), 3.0, R_MAX,
                              EPS, poly, leaf_max=lm)
+
+
+@pytest.mark.slow
+def test_tree_zeldovich128_sampled(sr, ctx, poly):
+    """The full 128^3 Zel'dovich box through the tree pass, sampled targets."""
+    p = W.config("zeldovich128")
+    t = to_dev(p)
+    a = accel_np(*sr.sr_force_tree(ctx, t["x"], t["y"], t["z"], t["m"], sr.Box.make(p.L), 3.0,
+                                   R_MAX, EPS, poly, leaf_max=128)[:3])
+    ctx.sync()
+    tg = np.sort(np.random.default_rng(77).choice(p.n, 2048, replace=False))
+    ref = O.force(p.x, p.y, p.z, p.m, p.L, R_MAX, EPS, poly.astype(np.float64), targets=tg)
+    check_accel(a[tg], ref, "tree zeldovich128")
+
+
+@pytest.mark.slow
+def test_tree_nfw256_sampled(sr, ctx, poly):
+    """The 256^3 clustered open share through the tree pass (leaf 128),
+    targets half from the densest cells, where the trees are deep."""
+    p = W.config("nfw256")
+    t = to_dev(p)
+    box = sr.Box.make(p.L, periodic=False, skin=p.skin)
+    a = accel_np(*sr.sr_force_tree(ctx, t["x"], t["y"], t["z"], t["m"], box, 3.0, R_MAX, EPS,
+                                   poly, leaf_max=128)[:3])
+    ctx.sync()
+    rng = np.random.default_rng(78)
+    _, _, cid = O.bin(p.x, p.y, p.z, 256.0, 3.0)
+    counts = np.bincount(cid)
+    dense = np.nonzero(counts[cid] >= np.sort(counts)[-50])[0]
+    tg = np.unique(np.concatenate([rng.choice(p.n, 128, replace=False),
+                                   rng.choice(dense, 128, replace=False)]))
+    ref = O.force(p.x, p.y, p.z, p.m, p.L, R_MAX, EPS, poly.astype(np.float64), periodic=False,
+                  skin=p.skin, targets=tg)
+    check_accel(a[tg], ref, "tree nfw256")
