@@ -160,6 +160,7 @@ def main():
     mom = torch.zeros(3, dtype=torch.float64, device=dev)
 
     useful, cand, _ = sr.sr_pair_stats(ctx, t["x"], t["y"], t["z"], box, args.cell, R_MAX)
+    ncell = sr.sr_grid_dims(box, args.cell)[1]
     log("pairs: useful %d candidates %d (waste %.2fx)" % (useful, cand, cand / max(useful, 1)))
 
     def step():
@@ -236,6 +237,14 @@ def main():
             "candidate_pairs": cand,
             "waste": cand / max(useful, 1),
             "prep_ms": prep_avg,
+            # binning + work items against the algorithmic bytes of binning:
+            # 16 B per particle (positions in, permutation out) plus the
+            # offsets, or 48 B per particle with the sorted float4 copy
+            "binning_bytes_min": 16 * p.n + 4 * (ncell + 1),
+            "binning_bytes_sorted": 48 * p.n + 4 * (ncell + 1),
+            "binning_effective_GBps_min": (16 * p.n + 4 * (ncell + 1)) / (prep_avg * 1e-3) / 1e9,
+            "binning_effective_GBps_sorted": (48 * p.n + 4 * (ncell + 1)) / (prep_avg * 1e-3)
+            / 1e9,
             "pair_loop_ms": force_avg,
             "pair_loop_useful_per_s": useful / (force_avg * 1e-3),
             "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
