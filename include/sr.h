@@ -220,6 +220,14 @@ int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox, const flo
                    float r_max, float eps, const float poly[6], float *ax, float *ay, float *az,
                    double *momentum3);
 
+/* ---- FP64 reductions on the device ------------------------------------ */
+
+/* Kinetic energy K = sum_i m_i |v_i|^2 / 2 in FP64 (device float32 inputs,
+ * *out a device double), reduced in a fixed order (bitwise reproducible).
+ * The companion of the momentum sum that sr_force returns. */
+int sr_kinetic(sr_ctx *ctx, const float *vx, const float *vy, const float *vz, const float *mass,
+               int64_t n, double *out);
+
 /* ---- RCB-tree variant (Sec. 2.4 RCB tree, Sec. 3.1 trees per fixed bin) - */
 
 /* sr_force computed with an RCB tree inside every chaining cell instead of
@@ -324,6 +332,7 @@ typedef struct sr_request {
     const float *mass;           /* HOST masses */
     double *out_x, *out_y, *out_z;   /* HOST final positions (written at completion) */
     float *out_vx, *out_vy, *out_vz; /* HOST final velocities */
+    double *out_kinetic;             /* HOST, optional: FP64 sum m |v|^2 / 2 of the final state */
 } sr_request;
 
 typedef struct sr_server_config {

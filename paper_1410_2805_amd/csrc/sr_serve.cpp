@@ -90,13 +90,15 @@ struct Req {
     float *vx = nullptr, *vy = nullptr, *vz = nullptr;
     float *m = nullptr, *ax = nullptr, *ay = nullptr, *az = nullptr;
     double *fx = nullptr, *fy = nullptr, *fz = nullptr;
+    double *kin = nullptr;  // kRedBlocks partials, then K
     hipEvent_t done = nullptr;
 };
 
 size_t state_bytes(int64_t n)
 {
     const size_t f = al((size_t)n * 4), d = al((size_t)n * 8);
-    return f /*cell3*/ + 3 * f /*o*/ + 3 * f /*v*/ + f /*m*/ + 3 * f /*a*/ + 3 * d /*f64*/;
+    return f /*cell3*/ + 3 * f /*o*/ + 3 * f /*v*/ + f /*m*/ + 3 * f /*a*/ + 3 * d /*f64*/ +
+           al((kRedBlocks + 1) * sizeof(double)) /*K*/;
 }
 
 void carve(Req &q, char *base)
@@ -113,6 +115,7 @@ void carve(Req &q, char *base)
     q.fx = (double *)p;
     q.fy = (double *)(p + d);
     q.fz = (double *)(p + 2 * d);
+    q.kin = (double *)(p + 3 * d);
 }
 
 size_t table_bytes(int slots)
@@ -419,6 +422,14 @@ extern "C" int sr_server_tick(sr_server *S, int *n_active)
             hipMemcpyAsync(q.r.out_vz, q.vz, n * 4, hipMemcpyDeviceToHost, ctx->stream) !=
                 hipSuccess)
             return sr_fail(ctx, SR_EDEVICE, "result copy failed");
+        if (q.r.out_kinetic) {
+            if ((rc = kinetic_enqueue(ctx, q.vx, q.vy, q.vz, q.m, (int)n, q.kin,
+                                      q.kin + kRedBlocks)))
+                return rc;
+            if (hipMemcpyAsync(q.r.out_kinetic, q.kin + kRedBlocks, sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+                return sr_fail(ctx, SR_EDEVICE, "result copy failed");
+        }
         if (hipEventRecord(q.done, ctx->stream) != hipSuccess)
             return sr_fail(ctx, SR_EDEVICE, "hipEventRecord failed");
         q.state = kDraining;

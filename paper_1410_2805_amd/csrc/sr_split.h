@@ -53,3 +53,7 @@ int ml_update_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float
                       float *oz, float *vx, float *vy, float *vz, const float *ax,
                       const float *ay, const float *az, const unsigned char *level, int m, int M,
                       double tau, double stream);
+
+// FP64 K = sum m |v|^2 / 2 into *out (device); part: kRedBlocks doubles.
+int kinetic_enqueue(sr_ctx *ctx, const float *vx, const float *vy, const float *vz,
+                    const float *m, int n, double *part, double *out);

@@ -284,6 +284,57 @@ __global__ __launch_bounds__(kBlock) void k_ml_update(SplitGeom sg, int n, int *
     cell3[i] = pack3(c);
 }
 
+// ---- FP64 kinetic energy K = sum_i m_i |v_i|^2 / 2 ---------------------------
+// Fixed partition into R contiguous chunks (R = clamp(ceil(n / 4096), 1,
+// kRedBlocks)), a fixed tree inside each block and over the partials:
+// bitwise reproducible.
+
+__global__ __launch_bounds__(256) void k_kinetic_partial(const float *__restrict__ vx,
+                                                         const float *__restrict__ vy,
+                                                         const float *__restrict__ vz,
+                                                         const float *__restrict__ m, int n,
+                                                         double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    int R = (n + 4095) / 4096;
+    R = R < 1 ? 1 : (R > kRedBlocks ? kRedBlocks : R);
+    const int chunk = (n + R - 1) / R;
+    const int lo = blockIdx.x * chunk;
+    const int hi = (int)blockIdx.x < R ? (lo + chunk < n ? lo + chunk : n) : lo;
+    double s = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += 256) {
+        const double a = vx[i], b = vy[i], c = vz[i];
+        s += 0.5 * (double)m[i] * (a * a + b * b + c * c);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_kinetic_final(const double *__restrict__ part,
+                                                       double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < kRedBlocks; k += 256)
+        s += part[k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *out = sh[0];
+}
+
 }  // namespace
 
 int split_geom(sr_ctx *ctx, const sr_box *box, double cell, SplitGeom *sg)
@@ -422,4 +473,30 @@ int ml_update_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float
                        sg, n, cell3, ox, oy, oz, vx, vy, vz, ax, ay, az, level, m, M, tau,
                        stream);
     return sr_check_launch(ctx, "k_ml_update");
+}
+
+int kinetic_enqueue(sr_ctx *ctx, const float *vx, const float *vy, const float *vz,
+                    const float *m, int n, double *part, double *out)
+{
+    hipLaunchKernelGGL(k_kinetic_partial, dim3(kRedBlocks), dim3(256), 0, ctx->stream, vx, vy, vz,
+                       m, n, part);
+    hipLaunchKernelGGL(k_kinetic_final, dim3(1), dim3(256), 0, ctx->stream, part, out);
+    return sr_check_launch(ctx, "k_kinetic");
+}
+
+extern "C" int sr_kinetic(sr_ctx *ctx, const float *vx, const float *vy, const float *vz,
+                          const float *mass, int64_t n, double *out)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    if (!out || n < 0 || n > INT_MAX || (n > 0 && (!vx || !vy || !vz || !mass)))
+        return sr_fail(ctx, SR_EINVAL, "bad size or NULL pointer");
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    int rc = sr_arena_reserve(ctx, kRedBlocks * sizeof(double));
+    if (rc)
+        return rc;
+    return kinetic_enqueue(ctx, vx, vy, vz, mass, (int)n, reinterpret_cast<double *>(ctx->arena),
+                           out);
 }

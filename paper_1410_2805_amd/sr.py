@@ -69,7 +69,7 @@ class Request(ctypes.Structure):
                 ("mass", ctypes.c_void_p),
                 ("out_x", ctypes.c_void_p), ("out_y", ctypes.c_void_p), ("out_z", ctypes.c_void_p),
                 ("out_vx", ctypes.c_void_p), ("out_vy", ctypes.c_void_p),
-                ("out_vz", ctypes.c_void_p)]
+                ("out_vz", ctypes.c_void_p), ("out_kinetic", ctypes.c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -154,6 +154,7 @@ def _load():
         "sr_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "sr_timing_collect": (ctypes.c_int, [P, ctypes.POINTER(f64), ctypes.POINTER(f64),
                                              ctypes.POINTER(i64)]),
+        "sr_kinetic": (ctypes.c_int, [P, P, P, P, P, i64, P]),
         "sr_force_tree": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, f32, f32, P, i32, P, P, P,
                                          P]),
         "sr_tree_leaves": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, i32, P,
@@ -189,7 +190,7 @@ def exported_symbols() -> list[str]:
             "sr_server_cancel", "sr_server_info_get", "sr_server_destroy",
             "sr_pm_create", "sr_pm_destroy", "sr_pm_bytes", "sr_pm_deposit", "sr_pm_fft",
             "sr_pm_force", "sr_pm_force_split", "sr_ksk_step", "sr_force_tree",
-            "sr_tree_leaves"]
+            "sr_tree_leaves", "sr_kinetic"]
 
 
 def _ptr(t):
@@ -403,6 +404,16 @@ def sr_force_tree(ctx: Context, x, y, z, m, box: Box, cell: float, r_max: float,
     return ax, ay, az, mom
 
 
+def sr_kinetic(ctx: Context, vx, vy, vz, m):
+    """FP64 sum m |v|^2 / 2 as a one-element float64 device tensor."""
+    n = int(vx.shape[0])
+    out = torch.zeros(1, dtype=torch.float64, device=vx.device)
+    ctx._bind_stream()
+    ctx._check(lib.sr_kinetic(ctx._h, _f32(vx, n, "vx"), _f32(vy, n, "vy"), _f32(vz, n, "vz"),
+                              _f32(m, n, "mass"), n, _ptr(out)))
+    return out
+
+
 def sr_tree_leaves(ctx: Context, x, y, z, m, box: Box, cell: float, leaf_max: int = 128):
     """(leaf index of every particle as an int32 device tensor, leaf count);
     waits."""
@@ -530,7 +541,10 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, L: float, steps: int, dt: float, pos64, vel, mass, out_pos, out_vel) -> int:
+    def submit(self, L: float, steps: int, dt: float, pos64, vel, mass, out_pos, out_vel,
+               out_kinetic=None) -> int:
+        """out_kinetic: optional float64 numpy array of one element that
+        receives the final state's FP64 kinetic energy."""
         import numpy as np
         n = int(mass.shape[0])
         arrs = [np.ascontiguousarray(pos64[:, d], dtype=np.float64) for d in range(3)]
@@ -543,10 +557,13 @@ class Server:
         r.x, r.y, r.z, r.vx, r.vy, r.vz, r.mass = (a.ctypes.data for a in arrs)
         r.out_x, r.out_y, r.out_z = (a.ctypes.data for a in out_pos)
         r.out_vx, r.out_vy, r.out_vz = (a.ctypes.data for a in out_vel)
+        if out_kinetic is not None:
+            assert out_kinetic.dtype == np.float64 and out_kinetic.size >= 1
+            r.out_kinetic = out_kinetic.ctypes.data
         rid = ctypes.c_int64()
         self.ctx._bind_stream()
         self.ctx._check(lib.sr_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
-        self._keep[int(rid.value)] = (arrs, out_pos, out_vel)
+        self._keep[int(rid.value)] = (arrs, out_pos, out_vel, out_kinetic)
         return int(rid.value)
 
     def tick(self) -> int:

@@ -370,3 +370,21 @@ def test_ksk_step_full_size(sr, ctx):
     ref = O.force(xh[:, 0], xh[:, 1], xh[:, 2], m, L, R_MAX, EPS, poly.astype(np.float64),
                   targets=tg)
     check_sr(_np(*so)[tg], ref, "step a_sr at 128^3")
+
+
+def test_kinetic_energy_fp64(sr, ctx):
+    """sum m |v|^2 / 2 in FP64 on the device: the plain FP64 sum to
+    rounding, bitwise reproducible, 0 for no particles."""
+    rng = np.random.default_rng(8)
+    n = 1_000_003
+    v = rng.normal(size=(n, 3)).astype(np.float32)
+    m = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    t = [_dev(v[:, d]) for d in range(3)]
+    k1 = sr.sr_kinetic(ctx, *t, _dev(m))
+    k2 = sr.sr_kinetic(ctx, *t, _dev(m))
+    ctx.sync()
+    ref = 0.5 * (m.astype(np.float64) * (v.astype(np.float64) ** 2).sum(1)).sum()
+    assert abs(float(k1) - ref) <= 1e-12 * ref
+    assert torch.equal(k1, k2)
+    e = torch.zeros(0, dtype=torch.float32, device="cuda:0")
+    assert float(sr.sr_kinetic(ctx, e, e, e, e)) == 0.0

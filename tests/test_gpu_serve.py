@@ -42,12 +42,12 @@ def _box(ngrid, seed, vscale=0.3):
     return pos, vel, mass
 
 
-def _submit(sr, srv, ngrid, steps, box):
+def _submit(sr, srv, ngrid, steps, box, kinetic=None):
     pos, vel, mass = box
     n = mass.shape[0]
     op = tuple(sr.pinned_empty(n, np.float64) for _ in range(3))
     ov = tuple(sr.pinned_empty(n, np.float32) for _ in range(3))
-    rid = srv.submit(float(ngrid), steps, DT, pos, vel, mass, op, ov)
+    rid = srv.submit(float(ngrid), steps, DT, pos, vel, mass, op, ov, out_kinetic=kinetic)
     return rid, op, ov
 
 
@@ -69,11 +69,16 @@ def test_result_follows_fp64_oracle(sr, ctx, poly):
     ng, steps = 14, 4
     box = _box(ng, 3)
     srv = _server(sr, ctx, poly)
+    kin = np.full(1, np.nan)
     try:
-        rid, op, ov = _submit(sr, srv, ng, steps, box)
+        rid, op, ov = _submit(sr, srv, ng, steps, box, kinetic=kin)
         _drain(srv, {rid})
     finally:
         srv.close()
+    # FP64 kinetic energy of the returned velocities (Sec. 2.6 units, m = 1)
+    v = np.stack(ov, 1).astype(np.float64)
+    k_ref = 0.5 * (box[2].astype(np.float64) * (v * v).sum(1)).sum()
+    assert abs(kin[0] - k_ref) <= 1e-12 * k_ref
     pos, vel = box[0].copy(), box[1].astype(np.float64)
     for _ in range(steps):
         pos, vel, _ = O.sks(pos, vel, box[2], float(ng), R_MAX, EPS, poly.astype(np.float64), DT)
