@@ -388,3 +388,47 @@ def test_kinetic_energy_fp64(sr, ctx):
     assert torch.equal(k1, k2)
     e = torch.zeros(0, dtype=torch.float32, device="cuda:0")
     assert float(sr.sr_kinetic(ctx, e, e, e, e)) == 0.0
+
+
+@pytest.mark.parametrize("ng", [256, 512, 1024])
+def test_fft_large_grids_separable(sr, ctx, ng):
+    """Up to the largest grid (1024^3, 24 GB of solver memory): a separable
+    input a(i) b(j) c(k) has the separable transform A(k1) B(k2) C(k3)
+    (1-D library FFTs); sampled entries checked, both directions."""
+    rng = np.random.default_rng(ng)
+    vec = [(rng.normal(size=ng) + 1j * rng.normal(size=ng)).astype(np.complex64) for _ in range(3)]
+    pmh = sr.PM(ctx, ng, float(ng))
+    try:
+        va, vb, vc = [torch.from_numpy(v).to("cuda:0") for v in vec]
+        d = (va[:, None, None] * vb[None, :, None]) * vc[None, None, :]
+        d = d.contiguous()
+        idx = rng.integers(0, ng, size=(4096, 3))
+        ti = torch.from_numpy(idx).to("cuda:0")
+        spec = [np.fft.fft(v.astype(np.complex128)) for v in vec]
+        for inverse in (False, True):
+            pmh.fft(d, inverse=inverse)
+            ctx.sync()
+            got = d[ti[:, 0], ti[:, 1], ti[:, 2]].cpu().numpy().astype(np.complex128)
+            if not inverse:
+                want = spec[0][idx[:, 0]] * spec[1][idx[:, 1]] * spec[2][idx[:, 2]]
+                scale = np.abs(spec[0]).max() * np.abs(spec[1]).max() * np.abs(spec[2]).max()
+            else:  # back to the input times ng^3
+                want = (vec[0][idx[:, 0]].astype(np.complex128) * vec[1][idx[:, 1]]
+                        * vec[2][idx[:, 2]]) * float(ng) ** 3
+                scale = np.abs(want).max()
+            err = np.abs(got - want).max() / scale
+            assert err <= 2e-6 * np.log2(ng ** 3), (ng, inverse, err)
+        del d
+    finally:
+        pmh.close()
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_force_256_grid_clustered(sr, ctx):
+    """The whole PM force on a 256^3 grid (lines of 256 in the FFT, 8 per
+    block) for a clustered set of 200,000 particles in a box of side 200."""
+    c = W.nfw_share(200_000, 200.0, 9, periodic=True, halo_cap=40_000)
+    pos = np.stack([c.x, c.y, c.z], 1)
+    tg = np.sort(np.random.default_rng(4).choice(c.n, 4096, replace=False))
+    _force_case(sr, ctx, pos, c.m, 256, 200.0, "clustered 256^3 grid", targets=tg)
