@@ -178,13 +178,20 @@ __device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long v, 
     return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
-// Deposit: one particle per lane, 8 fixed-point contributions each, added
-// to the grid with 64-bit integer atomics.  Along z, the upper corners of
+// Deposit: each block takes kDepBlock consecutive particles and their 8
+// fixed-point CIC contributions each.  When the block's particles fill a
+// small box of grid points (input in lattice or cell order does), the block
+// sums into a dense LDS window over that box first (64-bit LDS atomics) and
+// then adds each non-zero window point to the grid once.  Otherwise every
+// contribution goes to the grid directly, where along z the upper corners of
 // lane k are the lower corners of lane k + 1 whenever the two particles sit
-// in neighbouring cells of one (x, y) column (the common case for inputs in
-// lattice or cell order), so lane k + 1 takes those four values over by a
-// lane shuffle and one atomic serves both.  Integer sums make the result
-// independent of every order.
+// in neighbouring cells of one (x, y) column, so lane k + 1 takes those four
+// values over by a lane shuffle and one atomic serves both.  Integer sums
+// make the result independent of every order.
+constexpr int kDepPer = 2;                    // particles per thread
+constexpr int kDepBlock = kBlock * kDepPer;   // particles per block
+constexpr int kWin = 6144;                    // LDS window points (48 KiB)
+
 template <class Src>
 __global__ __launch_bounds__(kBlock) void k_pm_deposit(Src src, const float *__restrict__ m, int n,
                                                        PmGeo g, const unsigned *__restrict__ part,
@@ -192,49 +199,139 @@ __global__ __launch_bounds__(kBlock) void k_pm_deposit(Src src, const float *__r
                                                        unsigned long long *__restrict__ acc,
                                                        int *__restrict__ status)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int lane = threadIdx.x & 63;
+    __shared__ unsigned long long win[kWin];
+    __shared__ int red[6][kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int shift = fixed_shift(parts_max(part, nparts), n);
-    bool ok = false;
-    double f[3] = {0.0, 0.0, 0.0};
-    int i0[3] = {0, 0, 0}, i1[3] = {0, 0, 0};
-    double q = 0.0;
-    if (i < n) {
-        double p[3];
-        src.get(i, p);
-        if (!cic_setup(p, g, i0, i1, f)) {
-            atomicOr(status, kStatusMass);
-        } else {
-            const float mi = m[i];
-            if (mi >= 0.f && isfinite(mi) && mi != 0.f) {
-                ok = true;
-                q = ldexp((double)mi, shift);
+    bool ok[kDepPer];
+    double f[kDepPer][3], q[kDepPer];
+    int i0[kDepPer][3], i1[kDepPer][3];
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-1, -1, -1};
+#pragma unroll
+    for (int k = 0; k < kDepPer; ++k) {
+        const int i = blockIdx.x * kDepBlock + k * kBlock + threadIdx.x;
+        ok[k] = false;
+        q[k] = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f[k][d] = 0.0;
+            i0[k][d] = i1[k][d] = 0;
+        }
+        if (i < n) {
+            double p[3];
+            src.get(i, p);
+            if (!cic_setup(p, g, i0[k], i1[k], f[k])) {
+                atomicOr(status, kStatusMass);
+            } else {
+                const float mi = m[i];
+                if (mi >= 0.f && isfinite(mi) && mi != 0.f) {
+                    ok[k] = true;
+                    q[k] = ldexp((double)mi, shift);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        lo[d] = min(lo[d], i0[k][d]);
+                        hi[d] = max(hi[d], i0[k][d]);
+                    }
+                }
             }
         }
     }
-    const double wx[2] = {1.0 - f[0], f[0]}, wy[2] = {1.0 - f[1], f[1]};
-    const double wz0 = 1.0 - f[2], wz1 = f[2];
-    const int ix[2] = {i0[0], i1[0]}, iy[2] = {i0[1], i1[1]};
+    // the block's box of lower corners
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int d = 0; d < 3; ++d) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int row = (ix[a] * g.ng + iy[b]) * g.ng;
-            const double qab = q * wx[a] * wy[b];
-            unsigned long long v0 = ok ? (unsigned long long)llrint(qab * wz0) : 0ull;
-            const unsigned long long v1 = ok ? (unsigned long long)llrint(qab * wz1) : 0ull;
-            const int k0 = ok ? row + i0[2] : -1, k1 = ok ? row + i1[2] : -2;
-            const int rk = __shfl_up(k1, 1);
-            const unsigned long long rv = shfl_up_u64(v1, 1);
-            const bool take = lane > 0 && rk == k0;
-            if (take)
-                v0 += rv;
-            const bool given = __shfl_down((int)take, 1) != 0 && lane < 63;
-            if (v0)
-                atomicAdd(acc + k0, v0);
-            if (v1 && !given)
-                atomicAdd(acc + k1, v1);
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+            hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
         }
+        if (lane == 0) {
+            red[d][w] = lo[d];
+            red[3 + d][w] = hi[d];
+        }
+    }
+    __syncthreads();
+    int blo[3], dim[3];
+    long long vol = 1;
+    bool window = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int l = red[d][0], h = red[3 + d][0];
+        for (int k = 1; k < kBlock / 64; ++k) {
+            l = min(l, red[d][k]);
+            h = max(h, red[3 + d][k]);
+        }
+        blo[d] = l;
+        dim[d] = h - l + 2;  // upper corners included; they may lie past the face
+        window = window && h >= 0;
+        vol *= dim[d] > 0 ? dim[d] : 0;
+    }
+    window = window && vol > 0 && vol <= kWin;
+    if (window) {
+        for (int e = threadIdx.x; e < (int)vol; e += kBlock)
+            win[e] = 0ull;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kDepPer; ++k) {
+            if (!ok[k])
+                continue;
+            const int bx = i0[k][0] - blo[0], by = i0[k][1] - blo[1], bz = i0[k][2] - blo[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double qab = q[k] * (a ? f[k][0] : 1.0 - f[k][0]) *
+                                       (b ? f[k][1] : 1.0 - f[k][1]);
+                    const int row = ((bx + a) * dim[1] + (by + b)) * dim[2] + bz;
+                    const unsigned long long v0 = (unsigned long long)llrint(qab * (1.0 - f[k][2]));
+                    const unsigned long long v1 = (unsigned long long)llrint(qab * f[k][2]);
+                    if (v0)
+                        atomicAdd(&win[row], v0);
+                    if (v1)
+                        atomicAdd(&win[row + 1], v1);
+                }
+        }
+        __syncthreads();
+        const int plane = dim[1] * dim[2];
+        for (int e = threadIdx.x; e < (int)vol; e += kBlock) {
+            const unsigned long long v = win[e];
+            if (!v)
+                continue;
+            const int ex = e / plane, r = e - ex * plane, ey = r / dim[2], ez = r - ey * dim[2];
+            // window points past the upper face are the periodic images of
+            // the first grid plane
+            const int gx = blo[0] + ex, gy = blo[1] + ey, gz = blo[2] + ez;
+            atomicAdd(acc + ((long long)(gx < g.ng ? gx : gx - g.ng) * g.ng +
+                             (gy < g.ng ? gy : gy - g.ng)) * g.ng + (gz < g.ng ? gz : gz - g.ng),
+                      v);
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < kDepPer; ++k) {
+        const double wx[2] = {1.0 - f[k][0], f[k][0]}, wy[2] = {1.0 - f[k][1], f[k][1]};
+        const double wz0 = 1.0 - f[k][2], wz1 = f[k][2];
+        const int ix[2] = {i0[k][0], i1[k][0]}, iy[2] = {i0[k][1], i1[k][1]};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int row = (ix[a] * g.ng + iy[b]) * g.ng;
+                const double qab = q[k] * wx[a] * wy[b];
+                unsigned long long v0 = ok[k] ? (unsigned long long)llrint(qab * wz0) : 0ull;
+                const unsigned long long v1 = ok[k] ? (unsigned long long)llrint(qab * wz1) : 0ull;
+                const int k0 = ok[k] ? row + i0[k][2] : -1, k1 = ok[k] ? row + i1[k][2] : -2;
+                const int rk = __shfl_up(k1, 1);
+                const unsigned long long rv = shfl_up_u64(v1, 1);
+                const bool take = lane > 0 && rk == k0;
+                if (take)
+                    v0 += rv;
+                const bool given = __shfl_down((int)take, 1) != 0 && lane < 63;
+                if (v0)
+                    atomicAdd(acc + k0, v0);
+                if (v1 && !given)
+                    atomicAdd(acc + k1, v1);
+            }
+    }
 }
 
 // Fixed-point sums -> density (mass / Delta^3) as float32, clearing the
@@ -595,7 +692,7 @@ int deposit_enqueue(sr_pm *pm, const Src &src, const float *m, int n, int *npart
     int rc = sr_check_launch(ctx, "k_pm_mass_max");
     if (rc)
         return rc;
-    hipLaunchKernelGGL(k_pm_deposit<Src>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+    hipLaunchKernelGGL(k_pm_deposit<Src>, dim3((n + kDepBlock - 1) / kDepBlock), dim3(kBlock), 0,
                        ctx->stream, src, m, n, pm_geo(pm), pm->part, np, pm->acc, ctx->status);
     if ((rc = sr_check_launch(ctx, "k_pm_deposit")))
         return rc;
