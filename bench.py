@@ -462,6 +462,12 @@ def bench_step(args):
                    "pair_loop_ms": force_avg, "pair_loop_calls_per_step": nsub,
                    "pm_force_ms": pm_ms, "fft3d_ms": fft_ms,
                    "fft3d_GBps": fft_bytes / (fft_ms * 1e-3) / 1e9,
+                   # the PM's transform passes against HBM: algorithmic bytes of
+                   # one 3-D FFT (3 passes, read + write of complex64) per time
+                   "pm_fft_roofline": {"bound": "hbm", "kernel": "k_fft_lines",
+                                       "achieved": fft_bytes / (fft_ms * 1e-3) / 1e9,
+                                       "peak": 8000.0, "unit": "GB/s",
+                                       "frac": fft_bytes / (fft_ms * 1e-3) / 1e9 / 8000.0},
                    "candidate_pairs": [cand0, cand1], "useful_pairs": [useful0, useful1]},
         "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved,
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
