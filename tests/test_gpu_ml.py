@@ -125,3 +125,31 @@ def test_multilevel_parameters_rejected(sr, ctx):
                 sr.sr_ksk_step(ctx, pmh, st, box, prm, (z(), z(), z()), 0, (z(), z(), z()))
     finally:
         pmh.close()
+
+
+def test_multilevel_two_subcycles_matches_oracle(sr, ctx):
+    """Levels are reassigned at the start of every subcycle: two subcycles
+    per step, two steps, against the FP64 oracle step."""
+    L, pos, vel, m = _clustered(seed=6)
+    poly = gridfit.poly_coeffs()
+    dt = 0.02
+    pmh = sr.PM(ctx, 16, L)
+    try:
+        box, st = _state(sr, ctx, L, pos, vel, m)
+        gp, gv = _run(sr, ctx, pmh, box, st,
+                      sr.StepParams.make(R_MAX, EPS, poly, CELL, dt, 2, ml=(4, 1, 3)), steps=2)
+    finally:
+        pmh.close()
+    P, V, alr = pos, vel.astype(np.float64), None
+    for _ in range(2):
+        P, V, alr, _ = PMO.ksk_step(P, V, m.astype(np.float64), L, 16, R_MAX, EPS,
+                                    poly.astype(np.float64), dt, 2, a_lr=alr,
+                                    ml=(4, 1, 3, CELL))
+    dx = gp - P
+    dx -= L * np.round(dx / L)
+    vs = np.sqrt((V ** 2).sum(1).mean())
+    dv = np.abs(gv - V).max()
+    print("two subcycles x two steps: max|dv| %.3e (rms v %.3e) max|dx| %.3e"
+          % (dv, vs, np.abs(dx).max()))
+    assert dv <= 4e-5 * vs + 2e-5
+    assert np.abs(dx).max() <= 4e-5 * 2 * dt * vs + 2e-6

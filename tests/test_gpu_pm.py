@@ -432,3 +432,25 @@ def test_force_256_grid_clustered(sr, ctx):
     pos = np.stack([c.x, c.y, c.z], 1)
     tg = np.sort(np.random.default_rng(4).choice(c.n, 4096, replace=False))
     _force_case(sr, ctx, pos, c.m, 256, 200.0, "clustered 256^3 grid", targets=tg)
+
+
+def test_force_smallest_grid_and_empty_step(sr, ctx):
+    """ng = 8 (one block holds every line of a pass) against the oracle, and
+    a full step on no particles (a PM solve of an empty box, no kernels that
+    read particles)."""
+    rng = np.random.default_rng(12)
+    pos = (rng.random((500, 3)) * 8.0).astype(np.float32)
+    pos[pos >= np.float32(8.0)] = 0
+    _force_case(sr, ctx, pos, rng.uniform(0.5, 1.5, 500).astype(np.float32), 8, 8.0, "8^3 grid")
+    pmh = sr.PM(ctx, 16, 16.0)
+    try:
+        z = lambda dt=torch.float32: torch.zeros(0, dtype=dt, device="cuda:0")
+        st = {"cell3": z(torch.int32), "ox": z(), "oy": z(), "oz": z(), "vx": z(), "vy": z(),
+              "vz": z(), "m": z()}
+        for ml in (None, (4, 1, 3)):
+            prm = sr.StepParams.make(R_MAX, EPS, gridfit.poly_coeffs(), 3.0, 0.01, 2, ml=ml)
+            sr.sr_ksk_step(ctx, pmh, st, sr.Box.make(16.0), prm, (z(), z(), z()), 0,
+                           (z(), z(), z()))
+        ctx.sync()
+    finally:
+        pmh.close()
