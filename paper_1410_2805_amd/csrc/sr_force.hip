@@ -519,6 +519,28 @@ ForceParams make_params(float r_max, float eps, const float *poly)
     return fp;
 }
 
+void lpt_layout(Bump &b, int64_t bound, int **hist, int **off, int **part)
+{
+    const int nblk = lpt_blocks(bound);
+    *hist = b.take<int>((size_t)32 * nblk);
+    *off = b.take<int>((size_t)32 * nblk + 1);
+    scan_layout(b, 32 * nblk, part);
+}
+
+int lpt_sort_enqueue(sr_ctx *ctx, const int4 *items, const int *item_cost, const int *n_items,
+                     int64_t bound, int *hist, int *off, int *part, int *flag, int4 *out)
+{
+    int rc;
+    const int nblk = lpt_blocks(bound);
+    hipLaunchKernelGGL(k_lpt_hist, dim3(nblk), dim3(256), 0, ctx->stream, item_cost, n_items, nblk,
+                       hist);
+    if ((rc = scan_enqueue(ctx, hist, 32 * nblk, part, off, flag)))
+        return rc;
+    hipLaunchKernelGGL(k_lpt_scatter, dim3(nblk), dim3(256), 0, ctx->stream, items, item_cost,
+                       n_items, nblk, off, out);
+    return sr_check_launch(ctx, "k_lpt");
+}
+
 static int items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, int order)
 {
     int rc;

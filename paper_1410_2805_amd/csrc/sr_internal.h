@@ -199,6 +199,11 @@ int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int
                    Geom *g);
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly);
 ForceParams make_params(float r_max, float eps, const float *poly);
+// Longest-first order (stable counting sort on 5-bit cost buckets) of the
+// *n_items items; bound >= the item count.
+void lpt_layout(Bump &b, int64_t bound, int **hist, int **off, int **part);
+int lpt_sort_enqueue(sr_ctx *ctx, const int4 *items, const int *item_cost, const int *n_items,
+                     int64_t bound, int *hist, int *off, int *part, int *flag, int4 *out);
 int single_batch(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
                  int64_t n, const sr_box *box, double cell, float r_max, int xsplit, float *ax,
                  float *ay, float *az, Batch *B);

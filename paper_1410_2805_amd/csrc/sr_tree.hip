@@ -43,7 +43,10 @@ struct TreeScratch {
     int *chunks;        // [n] work items per leaf
     int *item_off;      // [n + 1]
     int *scan_part2;
-    int4 *items;        // [n + n / 16 + 1]
+    int4 *items;        // [n + n / 16 + 1] in leaf order
+    int *item_cost;     // [same] cost bucket floor(log2(neighbour-bin sources / S + 64))
+    int4 *items_lpt;    // [same] longest first
+    int *lpt_hist, *lpt_off, *lpt_part;
     int *flag0;         // [1] scan flag (kept 0)
 };
 
@@ -66,6 +69,9 @@ void tree_layout(Bump &b, int64_t n, int64_t ncell, TreeScratch &t)
     t.item_off = b.take<int>(nn + 1);
     scan_layout(b, (int)nn, &t.scan_part2);
     t.items = b.take<int4>((size_t)tree_item_bound(n));
+    t.item_cost = b.take<int>((size_t)tree_item_bound(n));
+    t.items_lpt = b.take<int4>((size_t)tree_item_bound(n));
+    lpt_layout(b, tree_item_bound(n), &t.lpt_hist, &t.lpt_off, &t.lpt_part);
     t.flag0 = b.take<int>(1);
 }
 
@@ -380,20 +386,45 @@ __global__ __launch_bounds__(64) void k_leaf_boxes(int n, const int *__restrict_
     }
 }
 
-// Items {leaf, first slot, targets, S | box << 5}, grid-stride over leaves.
-__global__ __launch_bounds__(256) void k_leaf_items(int n, const int *__restrict__ lscan,
+// Items {leaf, first slot, targets, S | box << 5}, grid-stride over leaves,
+// each with a cost bucket: the sources of the 27 neighbouring bins (an upper
+// bound of the interaction list) per lane group, plus fixed overhead.
+__global__ __launch_bounds__(256) void k_leaf_items(Batch B, int n, const int *__restrict__ lscan,
                                                     const int *__restrict__ leaf_start,
+                                                    const int *__restrict__ leaf_cell,
+                                                    const int *__restrict__ offsets,
                                                     const int *__restrict__ item_off,
-                                                    int4 *__restrict__ items)
+                                                    int4 *__restrict__ items,
+                                                    int *__restrict__ item_cost)
 {
     const int nleaves = lscan[n];
+    const Geom &g = B.one.g;
     for (int l = blockIdx.x * 256 + threadIdx.x; l < nleaves; l += gridDim.x * 256) {
         const int a = leaf_start[l], len = leaf_start[l + 1] - a;
         const int q = item_off[l + 1] - item_off[l];
+        int cx, cy, cz;
+        decode_cell(leaf_cell[l], g, cx, cy, cz);
+        long long src = 0;
+        for (int nb = 0; nb < 27; ++nb) {
+            int v[3] = {cx + nb % 3 - 1, cy + (nb / 3) % 3 - 1, cz + nb / 9 - 1};
+            bool ok = true;
+            for (int d = 0; d < 3; ++d) {
+                if (g.periodic)
+                    v[d] = v[d] < 0 ? v[d] + g.nc[d] : (v[d] >= g.nc[d] ? v[d] - g.nc[d] : v[d]);
+                else
+                    ok = ok && v[d] >= 0 && v[d] < g.nc[d];
+            }
+            if (ok) {
+                const int id = v[0] + g.nc[0] * (v[1] + g.nc[1] * v[2]);
+                src += offsets[id + 1] - offsets[id];
+            }
+        }
         for (int k = 0; k < q; ++k) {
             const int lo = (int)((long long)k * len / q);
             const int hi = (int)((long long)(k + 1) * len / q);
-            items[item_off[l] + k] = make_int4(l, a + lo, hi - lo, split_for(hi - lo));
+            const int S = split_for(hi - lo);
+            items[item_off[l] + k] = make_int4(l, a + lo, hi - lo, S);
+            item_cost[item_off[l] + k] = 63 - __clzll((unsigned long long)(src / S + 64));
         }
     }
 }
@@ -635,8 +666,12 @@ int tree_items(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const TreeScr
     if ((rc = scan_enqueue(ctx, t.chunks, n, t.scan_part2, t.item_off, t.flag0)))
         return rc;
     hipLaunchKernelGGL(k_leaf_items, dim3(blocks_of(n, 256) < 4096 ? blocks_of(n, 256) : 4096),
-                       dim3(256), 0, ctx->stream, n, t.lscan, t.leaf_start, t.item_off, t.items);
-    return sr_check_launch(ctx, "k_leaf_items");
+                       dim3(256), 0, ctx->stream, B, n, t.lscan, t.leaf_start, t.leaf_cell,
+                       s.offsets, t.item_off, t.items, t.item_cost);
+    if ((rc = sr_check_launch(ctx, "k_leaf_items")))
+        return rc;
+    return lpt_sort_enqueue(ctx, t.items, t.item_cost, t.item_off + n, tree_item_bound(n),
+                            t.lpt_hist, t.lpt_off, t.lpt_part, t.flag0, t.items_lpt);
 }
 
 int tree_setup(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
@@ -699,7 +734,7 @@ extern "C" int sr_force_tree(sr_ctx *ctx, const float *x, const float *y, const 
         int64_t grid = (int64_t)dev_cus * 32;
         grid = grid < ub ? grid : ub;
         hipLaunchKernelGGL(k_force_tree, dim3((unsigned)grid), dim3(64), 0, ctx->stream, B,
-                           t.items, t.item_off + n, s.sorted, s.perm, s.bin.mass_mixed,
+                           t.items_lpt, t.item_off + n, s.sorted, s.perm, s.bin.mass_mixed,
                            t.leaf_start, t.leaf_cell, t.leaf_lo, t.leaf_hi, t.cell_leaf, fp,
                            accept2);
         if ((rc = sr_check_launch(ctx, "k_force_tree")))
