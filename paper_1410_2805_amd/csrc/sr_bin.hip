@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
     if (chunk_count && lane < nc) {
         const int c = c0 + lane;
         const int lo = offsets[c], hi = offsets[c + 1];
-        int q = chunks_for(hi - lo);
+        int q = mesh_chunks_for(hi - lo);
         // an activity mask drops the cells without an active particle
         // (k_cell_active left 1 in chunk_count for the others)
         if (q && box_at(B, find_box(B.cstart, B.nb, c)).active)

@@ -9,8 +9,11 @@
 //   - sources are staged through LDS in tiles of kTile with their periodic
 //     image shift applied, then read back by broadcast;
 //   - when a cell holds few targets the 64 lanes are split into S groups that
-//     take every S-th source of a tile, and the groups' sums are added by
-//     cross-lane shuffles at the end;
+//     take disjoint slices of a tile, and the groups' sums are added in a
+//     fixed order through LDS at the end;
+//   - a lane may hold two targets, so that every source it reads serves both:
+//     an item takes whichever of one or two targets per lane leaves fewer
+//     lanes idle (up to 128 targets per item);
 //   - the pair loop is plain float32 VALU: one reciprocal square root,
 //     the polynomial in registers, the cutoff as a select (Sec. 3.1 describes
 //     the same select-based filtering inside the force loop).
@@ -51,17 +54,25 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
     frame_shift(g, cc, F);
     build_stencil(st, offsets + d.cbase, g, cx, cy, cz, F, lane);
 
-    const int part = lane / nt;
-    const int t = lane - part * nt;
+    // two targets per lane: lane t of a group holds targets t and t + ln
+    const bool two = item_two(item);
+    const int ln = two ? (nt + 1) >> 1 : nt;
+    const int part = lane / ln;
+    const int t = lane - part * ln;
     const bool has_target = part < S;
+    const bool has2 = two && has_target && t + ln < nt;
     const float4 pt = sorted[kb + t];
+    const float4 pt2 = sorted[kb + (has2 ? t + ln : t)];
     const bool pas = is_passive(pt, g);
+    const bool pas2 = is_passive(pt2, g);
     const float xi = pt.x + F[0], yi = pt.y + F[1], zi = pt.z + F[2];
+    const float xj = pt2.x + F[0], yj = pt2.y + F[1], zj = pt2.z + F[2];
     const bool uniform = mass_mixed[box] == 0;
     __syncthreads();
 
     float acx = 0.f, acy = 0.f, acz = 0.f;
-    if (__any(has_target && !pas)) {
+    float bcx = 0.f, bcy = 0.f, bcz = 0.f;
+    if (__any((has_target && !pas) || (has2 && !pas2))) {
         const int total = st.pbeg[kMaxPieces];
         // a pass stages `cap` sources (a multiple of the 4 S slice quantum, so
         // that padding stays inside the tile); the next pass's global loads
@@ -87,10 +98,22 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
             const int slice = cntp / S;
             const float4 *src = tile + (has_target ? part : 0) * slice;
             float tx = 0.f, ty = 0.f, tz = 0.f;
-            if (uniform)
+            if (two) {
+                float ux = 0.f, uy = 0.f, uz = 0.f;
+                if (uniform)
+                    pair_tile2<true>(src, slice, xi, yi, zi, xj, yj, zj, fp, tx, ty, tz, ux, uy,
+                                     uz);
+                else
+                    pair_tile2<false>(src, slice, xi, yi, zi, xj, yj, zj, fp, tx, ty, tz, ux, uy,
+                                      uz);
+                bcx += ux;
+                bcy += uy;
+                bcz += uz;
+            } else if (uniform) {
                 pair_tile<true>(src, slice, xi, yi, zi, fp, tx, ty, tz);
-            else
+            } else {
                 pair_tile<false>(src, slice, xi, yi, zi, fp, tx, ty, tz);
+            }
             acx += tx;
             acy += ty;
             acz += tz;
@@ -104,14 +127,18 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
             acx *= pt.w;
             acy *= pt.w;
             acz *= pt.w;
+            bcx *= pt2.w;
+            bcy *= pt2.w;
+            bcz *= pt2.w;
         }
     }
     // add the S group sums of each target in group order
     tile[lane] = make_float4(acx, acy, acz, 0.f);
+    tile[64 + lane] = make_float4(bcx, bcy, bcz, 0.f);
     __syncthreads();
     if (part == 0) {
         for (int q = 1; q < S; ++q) {
-            const float4 o = tile[t + q * nt];
+            const float4 o = tile[t + q * ln];
             acx += o.x;
             acy += o.y;
             acz += o.z;
@@ -120,6 +147,18 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
         d.ax[orig] = pas ? 0.f : acx;
         d.ay[orig] = pas ? 0.f : acy;
         d.az[orig] = pas ? 0.f : acz;
+        if (has2) {
+            for (int q = 1; q < S; ++q) {
+                const float4 o = tile[64 + t + q * ln];
+                bcx += o.x;
+                bcy += o.y;
+                bcz += o.z;
+            }
+            const int orig2 = perm[kb + t + ln] - d.pbase;
+            d.ax[orig2] = pas2 ? 0.f : bcx;
+            d.ay[orig2] = pas2 ? 0.f : bcy;
+            d.az[orig2] = pas2 ? 0.f : bcz;
+        }
     }
     __syncthreads();  // the tile is reused by the next item
 }
@@ -203,14 +242,21 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
     float F[3];
     frame_shift(g, cc, F);
     build_stencil(st, offsets + d.cbase, g, cx, cy, cz, F, lane);
-    const bool has_target = lane < nt;
-    const float4 pt = sorted[kb + (has_target ? lane : 0)];
-    const bool pas = is_passive(pt, g);
-    const bool act = has_target && !pas;
-    const float xi = pt.x + F[0], yi = pt.y + F[1], zi = pt.z + F[2];
+    // up to 128 targets: lane l counts for targets l and l + 64
+    bool act[2], has[2];
+    float xi[2], yi[2], zi[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        has[h] = lane + 64 * h < nt;
+        const float4 pt = sorted[kb + (has[h] ? lane + 64 * h : 0)];
+        act[h] = has[h] && !is_passive(pt, g);
+        xi[h] = pt.x + F[0];
+        yi[h] = pt.y + F[1];
+        zi[h] = pt.z + F[2];
+    }
     __syncthreads();
     const int total = st.pbeg[kMaxPieces];
-    int cntu = 0;
+    int cntu[2] = {0, 0};
     int p = 0;
     for (int g0 = 0; g0 < total; g0 += kTile) {
         const int cnt = total - g0 < kTile ? total - g0 : kTile;
@@ -219,17 +265,24 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const float4 s = tile[j];
-            const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-            const float se = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, fp.eps)));
-            cntu += se < fp.rcut ? 1 : 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float dx = s.x - xi[h], dy = s.y - yi[h], dz = s.z - zi[h];
+                const float se = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, fp.eps)));
+                cntu[h] += se < fp.rcut ? 1 : 0;
+            }
         }
         __syncthreads();
     }
-    cntu = act ? cntu - 1 : 0;  // the target itself is always in its stencil
-    if (has_target && per_target)
-        per_target[perm[kb + lane] - d.pbase] = cntu;
-    unsigned long long u = (unsigned long long)cntu;
-    unsigned long long c = act ? (unsigned long long)total : 0ull;
+    unsigned long long u = 0ull, c = 0ull;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cntu[h] = act[h] ? cntu[h] - 1 : 0;  // the target itself is always in its stencil
+        if (has[h] && per_target)
+            per_target[perm[kb + lane + 64 * h] - d.pbase] = cntu[h];
+        u += (unsigned long long)cntu[h];
+        c += act[h] ? (unsigned long long)total : 0ull;
+    }
     for (int o = 1; o < 64; o <<= 1) {
         u += __shfl_xor(u, o, 64);
         c += __shfl_xor(c, o, 64);
@@ -241,8 +294,9 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
 }
 
 // One thread per cell: the cell's targets split into chunk_count[c] nearly
-// equal chunks; each item also gets a cost bucket floor(log2(cost)) with
-// cost = stencil sources / S + 64 (wavefront iterations plus overhead).
+// equal chunks, each shaped by item_shape; each item also gets a cost bucket
+// floor(log2(cost)) with cost = stencil sources x the shape's cost per source
+// + 64 (wavefront iterations plus overhead).
 __global__ void k_items(Batch B, const int *__restrict__ offsets,
                         const int *__restrict__ item_off, int4 *__restrict__ items,
                         int *__restrict__ item_cost)
@@ -288,9 +342,10 @@ __global__ void k_items(Batch B, const int *__restrict__ offsets,
     for (int k = 0; k < q; ++k) {
         const int lo = (int)((long long)k * len / q);
         const int hi = (int)((long long)(k + 1) * len / q);
-        const int S = split_for(hi - lo);
-        items[item_off[c] + k] = make_int4(c, b + lo, hi - lo, S | (box << 5));
-        const long long cost = src / S + 64;
+        int tpl, S;
+        const float pass = item_shape(hi - lo, &tpl, &S);
+        items[item_off[c] + k] = make_int4(c, b + lo, hi - lo, S | (tpl - 1) << 5 | box << 6);
+        const long long cost = (long long)((float)src * pass) + 64;
         item_cost[item_off[c] + k] = 63 - __clzll((unsigned long long)cost);
     }
 }

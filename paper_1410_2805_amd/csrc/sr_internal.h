@@ -170,7 +170,8 @@ struct ForceScratch {
 
 constexpr int kRedBlocks = 512;    // FP64 reduction blocks per box (at most)
 constexpr int kLargeCell = 1024;   // cells above this are sorted by a whole block
-constexpr int kChunk = 64;         // maximum targets per force work item
+constexpr int kChunk = 64;         // maximum targets per work item at one target per lane
+constexpr int kChunk2 = 128;       // ... and at two targets per lane (chaining-mesh pass)
 constexpr int kMaxSplit = 16;      // at most 16 lane groups share one target
 constexpr int kLptBlock = 1024;    // items per block of the cost-bucket sort
 
@@ -249,6 +250,59 @@ __host__ __device__ inline int chunks_for(int n)
         for (int k = 0; k < q; ++k) {
             int sz = (k + 1) * n / q - k * n / q;
             c += 1.0f / (float)split_for(sz);
+        }
+        if (c < best) {
+            best = c;
+            bq = q;
+        }
+    }
+    return bq;
+}
+
+// Cost of one wavefront pass over a source at two targets per lane (two pair
+// evaluations per lane) relative to one target per lane: the ratio of the
+// instruction counts of the two pair loops per source (both loops issue the
+// same instructions per pair).
+constexpr float kTwoPerLane = 2.0f;
+
+// Shape of a chaining-mesh work item of nt targets (nt <= kChunk2): tpl
+// targets per lane (1, or 2 with lane t holding targets t and t + ceil(nt/2))
+// and S lane groups, whichever needs fewer issue slots per source; returns
+// that cost in full-wavefront passes per source.
+__host__ __device__ inline float item_shape(int nt, int *tpl, int *S)
+{
+    const float c1 = nt <= kChunk ? 1.0f / (float)split_for(nt) : 3.0e38f;
+    const int s2 = split_for((nt + 1) / 2);
+    const float c2 = kTwoPerLane / (float)s2;
+    if (c1 <= c2) {
+        *tpl = 1;
+        *S = split_for(nt);
+        return c1;
+    }
+    *tpl = 2;
+    *S = s2;
+    return c2;
+}
+
+// chunks_for for the chaining-mesh pass, whose items may take two targets per
+// lane: up to 256 targets the cheapest count under the same model with
+// item_shape's cost; beyond, chunks of at most kChunk2.  The count never
+// exceeds max(ceil(n / 64), n / 16) either.
+__host__ __device__ inline int mesh_chunks_for(int n)
+{
+    if (n <= 0)
+        return 0;
+    const int q0 = (n + kChunk2 - 1) / kChunk2;
+    if (n > 4 * kChunk)
+        return q0;
+    const int qmax = q0 > n / 16 ? q0 : n / 16;
+    float best = 3.0e38f;
+    int bq = q0;
+    for (int q = q0; q <= qmax; ++q) {
+        float c = 0.05f * (float)q;
+        for (int k = 0; k < q; ++k) {
+            int tpl, S;
+            c += item_shape((k + 1) * n / q - k * n / q, &tpl, &S);
         }
         if (c < best) {
             best = c;

@@ -185,43 +185,69 @@ __device__ __forceinline__ void load_tile(float4 (&pre)[kTile / 64], const Stenc
     }
 }
 
+// One pair of Eq. (force) for one lane: source s, target (xi, yi, zi);
+// adds f d (times the source mass unless uniform) to tx, ty, tz.
+template <bool kUniformMass>
+__device__ __forceinline__ void pair_one(const float4 s, float xi, float yi, float zi,
+                                         const ForceParams &fp, float &tx, float &ty, float &tz)
+{
+    const float dx = s.x - xi;
+    const float dy = s.y - yi;
+    const float dz = s.z - zi;
+    // se = s + eps; f = se^(-3/2) - q(se) with q(se) = p(se - eps)
+    const float se = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, fp.eps)));
+    const float rs = __builtin_amdgcn_rsqf(se);
+    const float rs2 = rs * rs;
+    const float tt = fmaf(rs2, rs, -fp.q0);
+    float h = fmaf(fp.nq[5], se, fp.nq[4]);
+    h = fmaf(h, se, fp.nq[3]);
+    h = fmaf(h, se, fp.nq[2]);
+    h = fmaf(h, se, fp.nq[1]);
+    float f = fmaf(h, se, tt);
+    f = se < fp.rcut ? f : 0.f;  // cutoff by select: also zeroes padding
+    if (!kUniformMass)
+        f *= s.w;
+    tx = fmaf(f, dx, tx);
+    ty = fmaf(f, dy, ty);
+    tz = fmaf(f, dz, tz);
+}
+
 // One tile of pair interactions for one lane: sources src[0 .. cnt) (cnt a
 // multiple of 4), target (xi, yi, zi); partial sums into tx, ty, tz.
 template <bool kUniformMass>
 __device__ __forceinline__ void pair_tile(const float4 *src, int cnt, float xi, float yi, float zi,
                                           const ForceParams &fp, float &tx, float &ty, float &tz)
 {
-    const float eps = fp.eps, rcut = fp.rcut, q0 = fp.q0;
-    const float n1 = fp.nq[1], n2 = fp.nq[2], n3 = fp.nq[3], n4 = fp.nq[4], n5 = fp.nq[5];
     for (int j = 0; j < cnt; j += 4) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 4; ++u)
+            pair_one<kUniformMass>(src[j + u], xi, yi, zi, fp, tx, ty, tz);
+    }
+}
+
+// pair_tile for two targets per lane: every source read from LDS serves both
+// (xi, yi, zi) -> t and (xj, yj, zj) -> u, each summed in source order (cnt
+// even; two sources per iteration keep the register count of pair_tile).
+template <bool kUniformMass>
+__device__ __forceinline__ void pair_tile2(const float4 *src, int cnt, float xi, float yi,
+                                           float zi, float xj, float yj, float zj,
+                                           const ForceParams &fp, float &tx, float &ty, float &tz,
+                                           float &ux, float &uy, float &uz)
+{
+    for (int j = 0; j < cnt; j += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
             const float4 s = src[j + u];
-            const float dx = s.x - xi;
-            const float dy = s.y - yi;
-            const float dz = s.z - zi;
-            // se = s + eps; f = se^(-3/2) - q(se) with q(se) = p(se - eps)
-            const float se = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-            const float rs = __builtin_amdgcn_rsqf(se);
-            const float rs2 = rs * rs;
-            const float tt = fmaf(rs2, rs, -q0);
-            float h = fmaf(n5, se, n4);
-            h = fmaf(h, se, n3);
-            h = fmaf(h, se, n2);
-            h = fmaf(h, se, n1);
-            float f = fmaf(h, se, tt);
-            f = se < rcut ? f : 0.f;  // cutoff by select: also zeroes padding
-            if (!kUniformMass)
-                f *= s.w;
-            tx = fmaf(f, dx, tx);
-            ty = fmaf(f, dy, ty);
-            tz = fmaf(f, dz, tz);
+            pair_one<kUniformMass>(s, xi, yi, zi, fp, tx, ty, tz);
+            pair_one<kUniformMass>(s, xj, yj, zj, fp, ux, uy, uz);
         }
     }
 }
 
-// Item layout: {cell (global), first sorted slot, targets, S | box << 5}.
+// Item layout: {cell (global), first sorted slot, targets, S | two << 5 |
+// box << 6}, two = 1 when each lane holds two targets.
 __device__ __forceinline__ int item_split(const int4 &it) { return it.w & 31; }
-__device__ __forceinline__ int item_box(const int4 &it) { return it.w >> 5; }
+__device__ __forceinline__ bool item_two(const int4 &it) { return (it.w >> 5) & 1; }
+__device__ __forceinline__ int item_box(const int4 &it) { return it.w >> 6; }
 
 }  // namespace
