@@ -395,7 +395,8 @@ __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int 
 // One wavefront per group of kSegGroup consecutive cells.  When the group
 // holds at most 64 particles, each lane takes one slot and ranks its index
 // among the smaller indices of the same cell (one pass for the whole group);
-// otherwise the cells are sorted one after the other.
+// otherwise the cells are sorted one after the other.  With chunk_count, the
+// pass also counts the force work items of each cell (mesh_chunks_for).
 __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restrict__ offsets,
                                                     int *__restrict__ perm,
                                                     int *__restrict__ large_list,
@@ -410,42 +411,46 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
     if (c0 >= B.ctot)
         return;
     const int nc = B.ctot - c0 < kSegGroup ? B.ctot - c0 : kSegGroup;
-    int bounds[kSegGroup + 1];
-#pragma unroll
-    for (int k = 0; k <= kSegGroup; ++k)
-        bounds[k] = __builtin_amdgcn_readfirstlane(offsets[c0 + (k < nc ? k : nc)]);
     if (chunk_count && lane < nc) {
         const int c = c0 + lane;
-        const int lo = offsets[c], hi = offsets[c + 1];
-        int q = mesh_chunks_for(hi - lo);
+        int q = mesh_chunks_for(offsets[c + 1] - offsets[c]);
         // an activity mask drops the cells without an active particle
         // (k_cell_active left 1 in chunk_count for the others)
         if (q && box_at(B, find_box(B.cstart, B.nb, c)).active)
             q = chunk_count[c] ? q : 0;
         chunk_count[c] = q;
     }
+    int bounds[kSegGroup + 1];
+#pragma unroll
+    for (int k = 0; k <= kSegGroup; ++k)
+        bounds[k] = __builtin_amdgcn_readfirstlane(offsets[c0 + (k < nc ? k : nc)]);
     const int b = bounds[0];
     const int total = bounds[kSegGroup] - b;
     if (total <= 64) {
-        // my slot, my cell (by the group's inner bounds), my index
+        // my slot, my cell (by the group's inner bounds), my index; the rank
+        // of my index among the indices of my own cell only, read from the
+        // lanes [cb - b, ce - b) by cross-lane permutes over the longest cell
         const int slot = b + lane;
         int mycell = 0;
 #pragma unroll
         for (int k = 1; k < kSegGroup; ++k)
             mycell += slot >= bounds[k] ? 1 : 0;
         const int v = lane < total ? perm[slot] : INT_MAX;
-        const int key_cell = lane < total ? mycell : kSegGroup;
+        int cb = bounds[0], ce = bounds[1], maxlen = bounds[1] - bounds[0];
+#pragma unroll
+        for (int k = 1; k < kSegGroup; ++k) {
+            cb = mycell >= k ? bounds[k] : cb;
+            ce = mycell >= k ? bounds[k + 1] : ce;
+            maxlen = bounds[k + 1] - bounds[k] > maxlen ? bounds[k + 1] - bounds[k] : maxlen;
+        }
+        const int first = cb - b, len = ce - cb;
         int rank = 0;
-        for (int k = 0; k < total; ++k) {
-            const int u = __builtin_amdgcn_readlane(v, k);
-            const int uc = __builtin_amdgcn_readlane(key_cell, k);
-            rank += (uc == key_cell && u < v) ? 1 : 0;
+#pragma unroll 4
+        for (int j = 0; j < maxlen; ++j) {
+            const int u = __shfl(v, first + (j < len ? j : 0), 64);
+            rank += (j < len && u < v) ? 1 : 0;
         }
         if (lane < total) {
-            int cb = bounds[0];
-#pragma unroll
-            for (int k = 1; k < kSegGroup; ++k)
-                cb = mycell >= k ? bounds[k] : cb;
             perm[cb + rank] = v;
             if (inv)
                 inv[v] = cb + rank;
@@ -585,7 +590,7 @@ __global__ void k_clear(ClearList cl)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kClear; ++k)
         if (cl.p[k] && i < cl.n[k])
             cl.p[k][i] = 0;
 }
@@ -593,7 +598,7 @@ __global__ void k_clear(ClearList cl)
 int clear_enqueue(sr_ctx *ctx, const ClearList &cl)
 {
     int64_t mx = 0;
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kClear; ++k)
         if (cl.p[k] && cl.n[k] > mx)
             mx = cl.n[k];
     if (mx <= 0)
@@ -614,6 +619,8 @@ void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
     s.large_count = b.take<int>(1);
     s.mass_mixed = b.take<int>((size_t)(nb > 0 ? nb : 1));
     s.scan_flag = b.take<int>(1);
+    s.lpt = b.take<int>(64);
+    s.n_items = b.take<int>(1);
 }
 
 // Enqueue the whole binning pass.  sorted and chunk_count may be NULL (then
@@ -632,6 +639,10 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
         cl.n[2] = B.nb;
         cl.p[3] = s.scan_flag;
         cl.n[3] = 1;
+        cl.p[4] = s.lpt;
+        cl.n[4] = 64;
+        cl.p[5] = s.n_items;
+        cl.n[5] = 1;
         if ((rc = clear_enqueue(ctx, cl)))
             return rc;
     }

@@ -293,68 +293,52 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
     }
 }
 
-// One thread per cell: the cell's targets split into chunk_count[c] nearly
-// equal chunks, each shaped by item_shape; each item also gets a cost bucket
-// floor(log2(cost)) with cost = stencil sources x the shape's cost per source
-// + 64 (wavefront iterations plus overhead).
-__global__ void k_items(Batch B, const int *__restrict__ offsets,
-                        const int *__restrict__ item_off, int4 *__restrict__ items,
-                        int *__restrict__ item_cost)
+// One thread per cell: its chunk_count[c] work items (cell_items), written at
+// a range the block reserves with one atomic on *n_items.  The order of the
+// items then depends on which block reserves first; no result does, since
+// every target is summed inside one item in a fixed order.
+__global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ offsets,
+                                               const int *__restrict__ chunk_count,
+                                               int4 *__restrict__ items,
+                                               int *__restrict__ item_cost,
+                                               int *__restrict__ n_items)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= B.ctot)
-        return;
-    const int q = item_off[c + 1] - item_off[c];
-    if (q == 0)
-        return;
-    const int box = find_box(B.cstart, B.nb, c);
-    const BoxDesc &d = box_at(B, box);
-    const Geom &g = d.g;
-    const int b = offsets[c];
-    const int len = offsets[c + 1] - b;
-    // stencil size (same rows as build_stencil, without the shifts)
-    int cx, cy, cz;
-    decode_cell(c - d.cbase, g, cx, cy, cz);
-    const int *off = offsets + d.cbase;
-    long long src = 0;
-    for (int r = 0; r < 9; ++r) {
-        int ny = cy + r % 3 - 1, nz = cz + r / 3 - 1;
-        if (g.periodic) {
-            ny = ny < 0 ? ny + g.nc[1] : (ny >= g.nc[1] ? ny - g.nc[1] : ny);
-            nz = nz < 0 ? nz + g.nc[2] : (nz >= g.nc[2] ? nz - g.nc[2] : nz);
-        } else if (ny < 0 || ny >= g.nc[1] || nz < 0 || nz >= g.nc[2]) {
-            continue;
-        }
-        const int row = g.nc[0] * (ny + g.nc[1] * nz);
-        const int lo = cx - g.hx, hi = cx + g.hx, n0 = g.nc[0];
-        if (g.periodic) {
-            if (lo < 0)
-                src += (off[row + hi + 1] - off[row]) + (off[row + n0] - off[row + lo + n0]);
-            else if (hi >= n0)
-                src += (off[row + n0] - off[row + lo]) + (off[row + hi - n0 + 1] - off[row]);
-            else
-                src += off[row + hi + 1] - off[row + lo];
-        } else {
-            const int a = lo > 0 ? lo : 0, e = hi < n0 - 1 ? hi : n0 - 1;
-            src += off[row + e + 1] - off[row + a];
-        }
+    __shared__ int wsum[4];
+    __shared__ int base;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int q = c < B.ctot ? chunk_count[c] : 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int tot;
+    const int ex = wave_exclusive_scan(q, lane, &tot);
+    if (lane == 0)
+        wsum[wid] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base = t > 0 ? atomicAdd(n_items, t) : 0;
     }
-    for (int k = 0; k < q; ++k) {
-        const int lo = (int)((long long)k * len / q);
-        const int hi = (int)((long long)(k + 1) * len / q);
-        int tpl, S;
-        const float pass = item_shape(hi - lo, &tpl, &S);
-        items[item_off[c] + k] = make_int4(c, b + lo, hi - lo, S | (tpl - 1) << 5 | box << 6);
-        const long long cost = (long long)((float)src * pass) + 64;
-        item_cost[item_off[c] + k] = 63 - __clzll((unsigned long long)cost);
+    __syncthreads();
+    if (q > 0) {
+        int first = base + ex;
+        for (int j = 0; j < wid; ++j)
+            first += wsum[j];
+        cell_items(B, offsets, c, q, first, items, item_cost);
     }
 }
 
-// Stable counting sort of items by decreasing cost bucket (key = 31 - bucket):
-// per-block key histograms, a scan in key-major order, stable scatter.
+// Longest-first order of the items: a counting sort by decreasing cost
+// bucket (key = 31 - bucket).  k_lpt_hist adds every block's key counts into
+// 32 global totals; k_lpt_scatter gives key k the range starting at the
+// totals of the keys before it, reserves one sub-range per (block, key) with
+// an atomic, and places its items there in their original order.  Which
+// block gets which sub-range depends on timing, so the item order inside a
+// key is not fixed -- results are: every target is summed entirely inside
+// one item, in a fixed order, whatever the order of the items.
+// lpt[0..31] are the key totals and lpt[32..63] the key cursors, both zero
+// on entry (the binning pass clears them).
 __global__ __launch_bounds__(256) void k_lpt_hist(const int *__restrict__ item_cost,
-                                                  const int *__restrict__ n_items, int nblk,
-                                                  int *__restrict__ hist)
+                                                  const int *__restrict__ n_items,
+                                                  int *__restrict__ lpt)
 {
     __shared__ int h[32];
     if (threadIdx.x < 32)
@@ -367,22 +351,39 @@ __global__ __launch_bounds__(256) void k_lpt_hist(const int *__restrict__ item_c
             atomicAdd(&h[31 - item_cost[i]], 1);
     }
     __syncthreads();
-    if (threadIdx.x < 32)
-        hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 32 && h[threadIdx.x] > 0)
+        atomicAdd(&lpt[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_lpt_scatter(const int4 *__restrict__ items,
                                                      const int *__restrict__ item_cost,
-                                                     const int *__restrict__ n_items, int nblk,
-                                                     const int *__restrict__ key_off,
+                                                     const int *__restrict__ n_items,
+                                                     int *__restrict__ lpt,
                                                      int4 *__restrict__ out)
 {
     __shared__ int run[32];
+    __shared__ int hcnt[32];
     __shared__ int wcnt[4][32];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (threadIdx.x < 32)
-        run[threadIdx.x] = 0;
     const int n = *n_items;
+    if ((int)blockIdx.x * kLptBlock >= n)
+        return;
+    if (threadIdx.x < 32)
+        hcnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int k = 0; k < kLptBlock / 256; ++k) {
+        const int i = blockIdx.x * kLptBlock + k * 256 + threadIdx.x;
+        if (i < n)
+            atomicAdd(&hcnt[31 - item_cost[i]], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        int base = 0;
+        for (int k = 0; k < (int)threadIdx.x; ++k)
+            base += lpt[k];
+        const int c = hcnt[threadIdx.x];
+        run[threadIdx.x] = c > 0 ? base + atomicAdd(&lpt[32 + threadIdx.x], c) : 0;
+    }
     for (int k = 0; k < kLptBlock / 256; ++k) {
         if (threadIdx.x < 128)
             wcnt[threadIdx.x >> 5][threadIdx.x & 31] = 0;
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const int4 *__restrict__ it
             int before = run[key];
             for (int w = 0; w < wid; ++w)
                 before += wcnt[w][key];
-            out[key_off[key * nblk + blockIdx.x] + before + rank] = items[i];
+            out[before + rank] = items[i];
         }
         __syncthreads();
         if (threadIdx.x < 32)
@@ -499,15 +500,9 @@ void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s)
     s.perm = b.take<int>(nn);
     s.sorted = b.take<float4>(nn);
     s.chunk_count = b.take<int>((size_t)ctot);
-    s.item_off = b.take<int>((size_t)ctot + 1);
-    scan_layout(b, (int)ctot, &s.scan_part2);
     s.items = b.take<int4>((size_t)ub);
     s.item_cost = b.take<int>((size_t)ub);
     s.items_lpt = b.take<int4>((size_t)ub);
-    const int nblk = lpt_blocks(ub);
-    s.lpt_hist = b.take<int>((size_t)32 * nblk);
-    s.lpt_off = b.take<int>((size_t)32 * nblk + 1);
-    scan_layout(b, 32 * nblk, &s.lpt_part);
     s.queue = b.take<int>(1);
     s.mom_part = b.take<double>((size_t)(nb > 0 ? nb : 1) * kRedBlocks * 3);
 }
@@ -574,49 +569,30 @@ ForceParams make_params(float r_max, float eps, const float *poly)
     return fp;
 }
 
-void lpt_layout(Bump &b, int64_t bound, int **hist, int **off, int **part)
-{
-    const int nblk = lpt_blocks(bound);
-    *hist = b.take<int>((size_t)32 * nblk);
-    *off = b.take<int>((size_t)32 * nblk + 1);
-    scan_layout(b, 32 * nblk, part);
-}
-
 int lpt_sort_enqueue(sr_ctx *ctx, const int4 *items, const int *item_cost, const int *n_items,
-                     int64_t bound, int *hist, int *off, int *part, int *flag, int4 *out)
+                     int64_t bound, int *lpt, int4 *out)
 {
-    int rc;
     const int nblk = lpt_blocks(bound);
-    hipLaunchKernelGGL(k_lpt_hist, dim3(nblk), dim3(256), 0, ctx->stream, item_cost, n_items, nblk,
-                       hist);
-    if ((rc = scan_enqueue(ctx, hist, 32 * nblk, part, off, flag)))
-        return rc;
+    hipLaunchKernelGGL(k_lpt_hist, dim3(nblk), dim3(256), 0, ctx->stream, item_cost, n_items, lpt);
     hipLaunchKernelGGL(k_lpt_scatter, dim3(nblk), dim3(256), 0, ctx->stream, items, item_cost,
-                       n_items, nblk, off, out);
+                       n_items, lpt, out);
     return sr_check_launch(ctx, "k_lpt");
 }
 
-static int items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, int order)
+// Binning with the per-cell item counts, the work items, then the
+// longest-first order when asked for.
+static int bin_items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, int order)
 {
     int rc;
-    if ((rc = scan_enqueue(ctx, s.chunk_count, B.ctot, s.scan_part2, s.item_off, s.bin.scan_flag)))
+    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count)))
         return rc;
     hipLaunchKernelGGL(k_items, dim3((B.ctot + 255) / 256), dim3(256), 0, ctx->stream, B,
-                       s.offsets, s.item_off, s.items, s.item_cost);
+                       s.offsets, s.chunk_count, s.items, s.item_cost, s.bin.n_items);
     if ((rc = sr_check_launch(ctx, "k_items")))
         return rc;
-    if (order == 1) {
-        const int nblk = lpt_blocks(item_bound(B.ntot, B.ctot));
-        const int *n_items = s.item_off + B.ctot;
-        hipLaunchKernelGGL(k_lpt_hist, dim3(nblk), dim3(256), 0, ctx->stream, s.item_cost,
-                           n_items, nblk, s.lpt_hist);
-        if ((rc = scan_enqueue(ctx, s.lpt_hist, 32 * nblk, s.lpt_part, s.lpt_off, s.bin.scan_flag)))
-            return rc;
-        hipLaunchKernelGGL(k_lpt_scatter, dim3(nblk), dim3(256), 0, ctx->stream, s.items,
-                           s.item_cost, n_items, nblk, s.lpt_off, s.items_lpt);
-        if ((rc = sr_check_launch(ctx, "k_lpt")))
-            return rc;
-    }
+    if (order == 1)
+        return lpt_sort_enqueue(ctx, s.items, s.item_cost, s.bin.n_items,
+                                item_bound(B.ntot, B.ctot), s.bin.lpt, s.items_lpt);
     return SR_OK;
 }
 
@@ -625,13 +601,11 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
 {
     int rc;
     sr_timing_mark(ctx, rec, 0);
-    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count)))
-        return rc;
-    if ((rc = items_enqueue(ctx, B, s, order)))
+    if ((rc = bin_items_enqueue(ctx, B, s, order)))
         return rc;
     sr_timing_mark(ctx, rec, 1);
     const int4 *items = order == 1 ? s.items_lpt : s.items;
-    const int *n_items = s.item_off + B.ctot;
+    const int *n_items = s.bin.n_items;
     if (B.ntot > 0) {
         if (persistent) {
             int dev_cus = 256;
@@ -835,9 +809,7 @@ extern "C" int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const 
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
     force_layout(b, n, B.ctot, 1, s);
-    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count)))
-        return rc;
-    if ((rc = items_enqueue(ctx, B, s, 0)))
+    if ((rc = bin_items_enqueue(ctx, B, s, 0)))
         return rc;
     // eps = 0 so that se = s and the test is s < r_max^2
     ForceParams fp = make_params(r_max, 0.0f, zero_poly);
@@ -846,7 +818,7 @@ extern "C" int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const 
         return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_pair_stats, dim3((unsigned)item_bound(n, B.ctot)), dim3(64), 0,
-                           ctx->stream, B, s.items, s.item_off + B.ctot, s.sorted, s.offsets,
+                           ctx->stream, B, s.items, s.bin.n_items, s.sorted, s.offsets,
                            s.perm, fp, per_target, st);
         if ((rc = sr_check_launch(ctx, "k_pair_stats")))
             return rc;

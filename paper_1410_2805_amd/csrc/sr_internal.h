@@ -141,12 +141,15 @@ struct BinScratch {
     int *large_count; // [1]
     int *mass_mixed;  // [nb] box b: 1 if any of its masses differs from its first
     int *scan_flag;   // [1] last-block counter of the scans (kept at 0)
+    int *lpt;         // [64] key totals and cursors of the longest-first item order
+    int *n_items;     // [1] force work items appended by k_items
 };
 
-// Up to four int buffers zeroed by one kernel launch.
+// Up to six int buffers zeroed by one kernel launch.
+constexpr int kClear = 6;
 struct ClearList {
-    int *p[4];
-    int64_t n[4];
+    int *p[kClear];
+    int64_t n[kClear];
 };
 
 // Everything a force pass needs beyond binning.
@@ -155,15 +158,10 @@ struct ForceScratch {
     int *offsets;     // [ctot + 1]
     int *perm;        // [ntot]
     float4 *sorted;   // [ntot] (x, y, z, m) in cell order
-    int *chunk_count; // [ctot]
-    int *item_off;    // [ctot + 1]; item_off[ctot] = number of items
-    int *scan_part2;
+    int *chunk_count; // [ctot] work items per cell (activity flags first, when masked)
     int4 *items;      // [item bound] in cell order
     int *item_cost;   // [item bound] cost bucket of each item
     int4 *items_lpt;  // [item bound] items by decreasing cost bucket
-    int *lpt_hist;    // [32 * lpt blocks] key-major per-block counts
-    int *lpt_off;     // [32 * lpt blocks + 1] their exclusive scan
-    int *lpt_part;
     int *queue;       // [1] persistent work counter
     double *mom_part; // [nb * kRedBlocks * 3]
 };
@@ -200,11 +198,10 @@ int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int
                    Geom *g);
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly);
 ForceParams make_params(float r_max, float eps, const float *poly);
-// Longest-first order (stable counting sort on 5-bit cost buckets) of the
-// *n_items items; bound >= the item count.
-void lpt_layout(Bump &b, int64_t bound, int **hist, int **off, int **part);
+// Longest-first order (counting sort on 5-bit cost buckets) of the *n_items
+// items; bound >= the item count; lpt: int[64], zero on entry (BinScratch).
 int lpt_sort_enqueue(sr_ctx *ctx, const int4 *items, const int *item_cost, const int *n_items,
-                     int64_t bound, int *hist, int *off, int *part, int *flag, int4 *out);
+                     int64_t bound, int *lpt, int4 *out);
 int single_batch(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
                  int64_t n, const sr_box *box, double cell, float r_max, int xsplit, float *ax,
                  float *ay, float *az, Batch *B);
@@ -310,4 +307,57 @@ __host__ __device__ inline int mesh_chunks_for(int n)
         }
     }
     return bq;
+}
+
+// Work items of cell c (global id), q of them, written at items[first ..
+// first + q): the cell's targets cut into q nearly equal chunks [k n / q,
+// (k + 1) n / q), each shaped by item_shape, as {c, first sorted slot,
+// targets, S | (tpl - 1) << 5 | box << 6}.  Each item also gets the cost
+// bucket floor(log2(cost)), cost = (sources of the cell's stencil) x (the
+// shape's cost per source) + 64 (wavefront iterations plus overhead).
+__device__ inline void cell_items(const Batch &B, const int *__restrict__ offsets, int c, int q,
+                                  int first, int4 *__restrict__ items, int *__restrict__ item_cost)
+{
+    const int box = find_box(B.cstart, B.nb, c);
+    const BoxDesc &d = box_at(B, box);
+    const Geom &g = d.g;
+    const int b = offsets[c];
+    const int len = offsets[c + 1] - b;
+    const int lc = c - d.cbase, plane = g.nc[0] * g.nc[1];
+    const int cz = lc / plane, cy = (lc - cz * plane) / g.nc[0];
+    const int cx = lc - cz * plane - cy * g.nc[0];
+    // stencil size: the 9 x-rows of 2 hx + 1 cells (shifts aside)
+    const int *off = offsets + d.cbase;
+    long long src = 0;
+    for (int r = 0; r < 9; ++r) {
+        int ny = cy + r % 3 - 1, nz = cz + r / 3 - 1;
+        if (g.periodic) {
+            ny = ny < 0 ? ny + g.nc[1] : (ny >= g.nc[1] ? ny - g.nc[1] : ny);
+            nz = nz < 0 ? nz + g.nc[2] : (nz >= g.nc[2] ? nz - g.nc[2] : nz);
+        } else if (ny < 0 || ny >= g.nc[1] || nz < 0 || nz >= g.nc[2]) {
+            continue;
+        }
+        const int row = g.nc[0] * (ny + g.nc[1] * nz);
+        const int lo = cx - g.hx, hi = cx + g.hx, n0 = g.nc[0];
+        if (g.periodic) {
+            if (lo < 0)
+                src += (off[row + hi + 1] - off[row]) + (off[row + n0] - off[row + lo + n0]);
+            else if (hi >= n0)
+                src += (off[row + n0] - off[row + lo]) + (off[row + hi - n0 + 1] - off[row]);
+            else
+                src += off[row + hi + 1] - off[row + lo];
+        } else {
+            const int a = lo > 0 ? lo : 0, e = hi < n0 - 1 ? hi : n0 - 1;
+            src += off[row + e + 1] - off[row + a];
+        }
+    }
+    for (int k = 0; k < q; ++k) {
+        const int lo = (int)((long long)k * len / q);
+        const int hi = (int)((long long)(k + 1) * len / q);
+        int tpl, S;
+        const float pass = item_shape(hi - lo, &tpl, &S);
+        items[first + k] = make_int4(c, b + lo, hi - lo, S | (tpl - 1) << 5 | box << 6);
+        const long long cost = (long long)((float)src * pass) + 64;
+        item_cost[first + k] = 63 - __clzll((unsigned long long)cost);
+    }
 }

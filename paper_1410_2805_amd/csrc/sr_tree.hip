@@ -46,7 +46,6 @@ struct TreeScratch {
     int4 *items;        // [n + n / 16 + 1] in leaf order
     int *item_cost;     // [same] cost bucket floor(log2(neighbour-bin sources / S + 64))
     int4 *items_lpt;    // [same] longest first
-    int *lpt_hist, *lpt_off, *lpt_part;
     int *flag0;         // [1] scan flag (kept 0)
 };
 
@@ -71,7 +70,6 @@ void tree_layout(Bump &b, int64_t n, int64_t ncell, TreeScratch &t)
     t.items = b.take<int4>((size_t)tree_item_bound(n));
     t.item_cost = b.take<int>((size_t)tree_item_bound(n));
     t.items_lpt = b.take<int4>((size_t)tree_item_bound(n));
-    lpt_layout(b, tree_item_bound(n), &t.lpt_hist, &t.lpt_off, &t.lpt_part);
     t.flag0 = b.take<int>(1);
 }
 
@@ -671,7 +669,7 @@ int tree_items(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const TreeScr
     if ((rc = sr_check_launch(ctx, "k_leaf_items")))
         return rc;
     return lpt_sort_enqueue(ctx, t.items, t.item_cost, t.item_off + n, tree_item_bound(n),
-                            t.lpt_hist, t.lpt_off, t.lpt_part, t.flag0, t.items_lpt);
+                            s.bin.lpt, t.items_lpt);
 }
 
 int tree_setup(sr_ctx *ctx, const float *x, const float *y, const float *z, const float *mass,
