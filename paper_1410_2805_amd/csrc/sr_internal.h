@@ -329,6 +329,7 @@ __device__ inline void cell_items(const Batch &B, const int *__restrict__ offset
     // stencil size: the 9 x-rows of 2 hx + 1 cells (shifts aside)
     const int *off = offsets + d.cbase;
     long long src = 0;
+#pragma unroll
     for (int r = 0; r < 9; ++r) {
         int ny = cy + r % 3 - 1, nz = cz + r / 3 - 1;
         if (g.periodic) {
@@ -351,9 +352,11 @@ __device__ inline void cell_items(const Batch &B, const int *__restrict__ offset
             src += off[row + e + 1] - off[row + a];
         }
     }
+    // k len fits in 32 bits below 46341 targets (q <= len)
+    const bool small = len <= 46340;
     for (int k = 0; k < q; ++k) {
-        const int lo = (int)((long long)k * len / q);
-        const int hi = (int)((long long)(k + 1) * len / q);
+        const int lo = small ? k * len / q : (int)((long long)k * len / q);
+        const int hi = small ? (k + 1) * len / q : (int)((long long)(k + 1) * len / q);
         int tpl, S;
         const float pass = item_shape(hi - lo, &tpl, &S);
         items[first + k] = make_int4(c, b + lo, hi - lo, S | (tpl - 1) << 5 | box << 6);
