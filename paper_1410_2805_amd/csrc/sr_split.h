@@ -33,11 +33,13 @@ int split_to_f64_enqueue(sr_ctx *ctx, const int *cell3, const float *ox, const f
 // mode 0: stream half step; mode 1: kick then stream half step.
 int slot_update_enqueue(sr_ctx *ctx, const SlotState *slots, const int *start, int nslot,
                         int ntot, int mode);
-// One box: v += a * kick (a may be null: no kick), then o += v * stream in
-// FP64 with re-homing (stream == 0: no stream).
+// One box: v += a * kick (a may be null: no kick), then nstream times
+// o += v * stream in FP64 with re-homing (stream == 0: no stream); two
+// streams are bitwise two calls with one.
 int kick_stream_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
                         float *oz, float *vx, float *vy, float *vz, const float *ax,
-                        const float *ay, const float *az, float kick, double stream);
+                        const float *ay, const float *az, float kick, double stream,
+                        int nstream = 1);
 
 // Multilevel stepping (Sec. 3.1, Eq. (kicks)) on one box of split state.
 // level[i] = clamp(floor(count * ncell / n) / d + 1, lmin, lmax) from the

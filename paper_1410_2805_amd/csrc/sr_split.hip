@@ -149,9 +149,11 @@ __global__ __launch_bounds__(kBlock) void k_slot_update(const SlotState *__restr
     S.cell3[li] = pack3(c);
 }
 
-// One box of split state: kick v += a * kick (when a is given), then stream
-// o += v * stream in FP64 with re-homing (stream == 0: kick only).  The
-// arithmetic of each map is that of k_slot_update.
+// One box of split state: kick v += a * kick (when a is given), then
+// nstream times stream o += v * stream in FP64 with re-homing (stream == 0:
+// kick only).  Each stream rounds the offset to float32 as a separate launch
+// would, so two streams here are bitwise two launches.  The arithmetic of
+// each map is that of k_slot_update.
 __global__ __launch_bounds__(kBlock) void k_kick_stream(SplitGeom sg, int n, int *__restrict__ cell3,
                                                         float *__restrict__ ox,
                                                         float *__restrict__ oy,
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_stream(SplitGeom sg, int n, int
                                                         const float *__restrict__ ax,
                                                         const float *__restrict__ ay,
                                                         const float *__restrict__ az, float kick,
-                                                        double stream)
+                                                        double stream, int nstream)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
@@ -183,9 +185,13 @@ __global__ __launch_bounds__(kBlock) void k_kick_stream(SplitGeom sg, int n, int
     float *o[3] = {ox, oy, oz};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double off = (double)o[k][i] + (double)v[k] * stream;
-        rehome(off, c[k], sg.h[k], sg.nc[k]);
-        o[k][i] = (float)off;
+        float of = o[k][i];
+        for (int s = 0; s < nstream; ++s) {
+            double off = (double)of + (double)v[k] * stream;
+            rehome(off, c[k], sg.h[k], sg.nc[k]);
+            of = (float)off;
+        }
+        o[k][i] = of;
     }
     cell3[i] = pack3(c);
 }
@@ -426,13 +432,13 @@ extern "C" int sr_split_to_f64(sr_ctx *ctx, const int32_t *cell3, const float *o
 
 int kick_stream_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
                         float *oz, float *vx, float *vy, float *vz, const float *ax,
-                        const float *ay, const float *az, float kick, double stream)
+                        const float *ay, const float *az, float kick, double stream, int nstream)
 {
     if (n <= 0)
         return SR_OK;
     hipLaunchKernelGGL(k_kick_stream, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
                        ctx->stream, sg, n, cell3, ox, oy, oz, vx, vy, vz, ax, ay, az, kick,
-                       stream);
+                       stream, nstream);
     return sr_check_launch(ctx, "k_kick_stream");
 }
 

@@ -123,14 +123,13 @@ extern "C" int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, fl
                                   half_dt, half_tau)))
         return rc;
     for (int c = 0; c < p->n_sub; ++c) {
-        if (c > 0 && (rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, nullptr,
-                                               nullptr, nullptr, 0.f, half_tau)))
-            return rc;
         if ((rc = sr_force_split(ctx, cell3, ox, oy, oz, mass, n, box, p->cell, p->r_max, p->eps,
                                  p->poly, sr_ax, sr_ay, sr_az, nullptr)))
             return rc;
+        // the kick, this subcycle's last half stream and, before another
+        // subcycle, the next one's first half stream: one launch
         if ((rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, sr_ax, sr_ay,
-                                      sr_az, (float)tau, half_tau)))
+                                      sr_az, (float)tau, half_tau, c + 1 < p->n_sub ? 2 : 1)))
             return rc;
     }
     if ((rc = pm_force_split_enqueue(pm, cell3, ox, oy, oz, mass, ni, sg.h, lr_ax, lr_ay, lr_az)))
