@@ -379,14 +379,17 @@ __global__ __launch_bounds__(64) void k_leaf_boxes(int n, const int *__restrict_
         if (lane == 0) {
             leaf_lo[l] = make_float4(lo[0], lo[1], lo[2], 0.f);
             leaf_hi[l] = make_float4(hi[0], hi[1], hi[2], 0.f);
+            // chunks of at most 64 targets: larger chunks at two targets per
+            // lane measured slower here (fewer, longer items)
             chunks[l] = chunks_for(e - a);
         }
     }
 }
 
-// Items {leaf, first slot, targets, S | box << 5}, grid-stride over leaves,
-// each with a cost bucket: the sources of the 27 neighbouring bins (an upper
-// bound of the interaction list) per lane group, plus fixed overhead.
+// Items {leaf, first slot, targets, S | (tpl - 1) << 5}, shaped by item_shape
+// (one or two targets per lane), grid-stride over leaves, each with a cost
+// bucket: the sources of the 27 neighbouring bins (an upper bound of the
+// interaction list) times the shape's cost per source, plus fixed overhead.
 __global__ __launch_bounds__(256) void k_leaf_items(Batch B, int n, const int *__restrict__ lscan,
                                                     const int *__restrict__ leaf_start,
                                                     const int *__restrict__ leaf_cell,
@@ -420,9 +423,11 @@ __global__ __launch_bounds__(256) void k_leaf_items(Batch B, int n, const int *_
         for (int k = 0; k < q; ++k) {
             const int lo = (int)((long long)k * len / q);
             const int hi = (int)((long long)(k + 1) * len / q);
-            const int S = split_for(hi - lo);
-            items[item_off[l] + k] = make_int4(l, a + lo, hi - lo, S);
-            item_cost[item_off[l] + k] = 63 - __clzll((unsigned long long)(src / S + 64));
+            int tpl, S;
+            const float pass = item_shape(hi - lo, &tpl, &S);
+            items[item_off[l] + k] = make_int4(l, a + lo, hi - lo, S | (tpl - 1) << 5);
+            const long long cost = (long long)((float)src * pass) + 64;
+            item_cost[item_off[l] + k] = 63 - __clzll((unsigned long long)cost);
         }
     }
 }
@@ -449,7 +454,7 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
                                   const int *__restrict__ cell_leaf, const ForceParams &fp,
                                   float accept2, float4 *tile, Stencil &st, int lane)
 {
-    const int leaf = item.x, kb = item.y, nt = item.z, S = item.w & 31;
+    const int leaf = item.x, kb = item.y, nt = item.z, S = item_split(item);
     const BoxDesc &d = B.one;
     const Geom &g = d.g;
     int cx, cy, cz;
@@ -461,17 +466,25 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
     const float tlo[3] = {tl.x + F[0], tl.y + F[1], tl.z + F[2]};
     const float thi[3] = {th.x + F[0], th.y + F[1], th.z + F[2]};
 
-    const int part = lane / nt;
-    const int t = lane - part * nt;
+    // two targets per lane: lane t of a group holds targets t and t + ln
+    const bool two = item_two(item);
+    const int ln = two ? (nt + 1) >> 1 : nt;
+    const int part = lane / ln;
+    const int t = lane - part * ln;
     const bool has_target = part < S;
+    const bool has2 = two && has_target && t + ln < nt;
     const float4 pt = sorted[kb + t];
+    const float4 pt2 = sorted[kb + (has2 ? t + ln : t)];
     const bool pas = is_passive(pt, g);
+    const bool pas2 = is_passive(pt2, g);
     const float xi = pt.x + F[0], yi = pt.y + F[1], zi = pt.z + F[2];
+    const float xj = pt2.x + F[0], yj = pt2.y + F[1], zj = pt2.z + F[2];
     const bool uniform = mass_mixed[0] == 0;
-    const bool work = __any(has_target && !pas);
+    const bool work = __any((has_target && !pas) || (has2 && !pas2));
     const int quantum = 4 * S;
     const int cap = kTile / quantum * quantum;
     float acx = 0.f, acy = 0.f, acz = 0.f;
+    float bcx = 0.f, bcy = 0.f, bcz = 0.f;
     int npiece = 0, total = 0;
 
     // runs the staged pieces through the pair loop and empties the list
@@ -498,10 +511,22 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
                 const int slice = cntp / S;
                 const float4 *src = tile + (has_target ? part : 0) * slice;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
-                if (uniform)
+                if (two) {
+                    float ux = 0.f, uy = 0.f, uz = 0.f;
+                    if (uniform)
+                        pair_tile2<true>(src, slice, xi, yi, zi, xj, yj, zj, fp, tx, ty, tz, ux,
+                                         uy, uz);
+                    else
+                        pair_tile2<false>(src, slice, xi, yi, zi, xj, yj, zj, fp, tx, ty, tz, ux,
+                                          uy, uz);
+                    bcx += ux;
+                    bcy += uy;
+                    bcz += uz;
+                } else if (uniform) {
                     pair_tile<true>(src, slice, xi, yi, zi, fp, tx, ty, tz);
-                else
+                } else {
                     pair_tile<false>(src, slice, xi, yi, zi, fp, tx, ty, tz);
+                }
                 acx += tx;
                 acy += ty;
                 acz += tz;
@@ -585,12 +610,16 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
         acx *= pt.w;
         acy *= pt.w;
         acz *= pt.w;
+        bcx *= pt2.w;
+        bcy *= pt2.w;
+        bcz *= pt2.w;
     }
     tile[lane] = make_float4(acx, acy, acz, 0.f);
+    tile[64 + lane] = make_float4(bcx, bcy, bcz, 0.f);
     __syncthreads();
     if (part == 0) {
         for (int q = 1; q < S; ++q) {
-            const float4 o = tile[t + q * nt];
+            const float4 o = tile[t + q * ln];
             acx += o.x;
             acy += o.y;
             acz += o.z;
@@ -599,6 +628,18 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
         d.ax[orig] = pas ? 0.f : acx;
         d.ay[orig] = pas ? 0.f : acy;
         d.az[orig] = pas ? 0.f : acz;
+        if (has2) {
+            for (int q = 1; q < S; ++q) {
+                const float4 o = tile[64 + t + q * ln];
+                bcx += o.x;
+                bcy += o.y;
+                bcz += o.z;
+            }
+            const int orig2 = perm[kb + t + ln];
+            d.ax[orig2] = pas2 ? 0.f : bcx;
+            d.ay[orig2] = pas2 ? 0.f : bcy;
+            d.az[orig2] = pas2 ? 0.f : bcz;
+        }
     }
     __syncthreads();
 }
