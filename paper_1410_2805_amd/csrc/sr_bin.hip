@@ -5,16 +5,19 @@
 //
 //   k_cellid   cell of each particle in FP64, histogram by atomic increment
 //              (the returned old count is an arrival rank, unordered)
-//   scan       three-phase exclusive prefix sum with wavefront scans
+//   scan       exclusive prefix sum: tile sums (the last block to finish
+//              scans the tile partials), then the per-tile down pass
 //   k_scatter  perm[offsets[cell] + rank] = i (grouped by cell, unordered
 //              inside a cell)
 //   k_segsort  restores stability: the slots of one cell hold that cell's
 //              original indices, so sorting them ascending is exactly the
-//              stable order.  One wavefront per cell: registers (<= 64),
-//              wavefront-private LDS bitonic sort (<= 1024); larger cells go
-//              to k_segsort_large (one block, LDS-sorted runs merged by rank).
-//              The same pass gathers the sorted float4 (x, y, z, m) copy and
-//              counts force work items per cell.
+//              stable order.  Four small cells per wavefront, each index
+//              ranked among its own cell's; cells up to 1024 by one
+//              wavefront (registers, or a wavefront-private LDS bitonic
+//              sort); larger cells go to k_segsort_large (one block,
+//              LDS-sorted runs merged by rank).  The pass writes the inverse
+//              permutation and, for the force pass, the work items per cell.
+//   k_gather   the sorted float4 (x, y, z, m) copy, through the inverse.
 // All kernels work on a batch of boxes whose particles and cells are numbered
 // consecutively; one box is a batch of one.
 #include <climits>
