@@ -54,7 +54,8 @@ enum {
     SR_ERANGE = -34   /* device-detected: coordinate outside [0, L) or NaN */
 };
 
-/* Box [0, len[0]) x [0, len[1]) x [0, len[2]).
+/* Box [0, len[0]) x [0, len[1]) x [0, len[2]), each side at most 131072
+ * (SR_EINVAL beyond) and exactly representable in float32.
  *   periodic != 0 : periodic in all three axes, minimum-image separations.
  *   periodic == 0 : open domain of an overloaded node (Sec. 2.2); particles
  *                   whose distance to the nearest face is < skin (strictly,
@@ -153,9 +154,13 @@ int sr_force(sr_ctx *ctx, const float *x, const float *y, const float *z, const 
  *   *useful     : directed pairs (i, j), i != j, i not passive, with the
  *                 float32 s_ij < r_max^2 -- the interactions Eq. (force)
  *                 requires.
- *   *candidates : directed pairs the chaining mesh presents to the force
- *                 loop: sum over non-passive targets of the particle count
- *                 of their 27 neighbour cells.
+ *   *candidates : directed pairs the force loop evaluates: sum over
+ *                 non-passive targets of the sources of their neighbour
+ *                 cells that pass the work item's box test (sources whose
+ *                 distance to the bounding box of the item's targets is
+ *                 within r_max; the others cannot interact with any of
+ *                 them).  Both counts use the work items of the current
+ *                 tuning.
  *   per_target  : optional device int32[n]: useful partners of each particle
  *                 (original order).
  * *useful and *candidates are HOST pointers; this call waits for the
@@ -170,7 +175,9 @@ int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const float *z, i
  *   xsplit     : 1..4 sub-cells per chaining cell along x.  The x-contiguous
  *                rows of the 27-cell search then span 2 + 1/xsplit chaining
  *                cells instead of 3, so fewer candidate pairs are tested; work
- *                items get smaller.  Default 2.
+ *                items get smaller.  Default 1: with the box test of the
+ *                pair loop (see sr_pair_stats), finer sub-cells save
+ *                little more and cost more items.
  *   order      : 0 work items in cell order; 1 by decreasing cost bucket
  *                (longest first), default.
  *   persistent : 0 one workgroup per work item (default); 1 a fixed grid of

@@ -71,6 +71,11 @@ int sr_make_geom(sr_ctx *ctx, const sr_box *box, double cell, Geom *g, int xspli
         g->lenf[d] = (float)box->len[d];
         g->nc[d] = dims[d];
         g->w[d] = box->len[d] / (double)dims[d];
+        // the pair loop pads tiles with sources at 1e6 on every axis (kFar,
+        // sr_pair.h): a bounded side keeps them beyond every cutoff from
+        // every real particle
+        if (box->len[d] > kMaxSide)
+            return sr_fail(ctx, SR_EINVAL, "box side %g exceeds %g", box->len[d], kMaxSide);
         if ((double)g->lenf[d] != box->len[d])
             return sr_fail(ctx, SR_EINVAL, "box side %g is not exactly representable in float32",
                            box->len[d]);

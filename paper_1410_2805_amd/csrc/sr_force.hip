@@ -79,23 +79,24 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
         // are issued before the current pass computes
         const int quantum = 4 * S;
         const int cap = kTile / quantum * quantum;
+        const int qrecip = quantum_recip(quantum);
+        // sources outside the cutoff of the whole box of the item's targets
+        // are dropped before they reach the tile
+        const TargetBox tb = target_box(xi, yi, zi, xj, yj, zj);
         float4 pre[kTile / 64];
         int p = 0;
         int g0 = 0;
         int cnt = total < cap ? total : cap;
         load_tile(pre, st, sorted, g0, cnt, lane, p);
         for (;;) {
-            const int cntp = (cnt + quantum - 1) / quantum * quantum;
-#pragma unroll
-            for (int k = 0; k < kTile / 64; ++k)
-                if (lane + 64 * k < cntp)
-                    tile[lane + 64 * k] = pre[k];
+            // kept sources, rounded up to the quantum with entries that add zero
+            const int nq = quanta_of(store_tile_kept(tile, pre, tb, fp, lane), quantum, qrecip);
             __syncthreads();
             const int g1 = g0 + cnt;
             const int cnt1 = total - g1 < cap ? total - g1 : cap;
             if (cnt1 > 0)
                 load_tile(pre, st, sorted, g1, cnt1, lane, p);
-            const int slice = cntp / S;
+            const int slice = 4 * nq;
             const float4 *src = tile + (has_target ? part : 0) * slice;
             float tx = 0.f, ty = 0.f, tz = 0.f;
             if (two) {
@@ -256,14 +257,20 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
     }
     __syncthreads();
     const int total = st.pbeg[kMaxPieces];
+    // the force pass's box test, so that the counts cover exactly the sources
+    // it evaluates (and a useful pair it dropped would show in per_target)
+    const TargetBox tb = target_box(xi[0], yi[0], zi[0], xi[1], yi[1], zi[1]);
     int cntu[2] = {0, 0};
+    int kept = 0;
     int p = 0;
     for (int g0 = 0; g0 < total; g0 += kTile) {
         const int cnt = total - g0 < kTile ? total - g0 : kTile;
-        const int cntp = (cnt + 63) & ~63;
-        stage_tile(tile, st, sorted, g0, cnt, cntp, lane, p);
+        float4 pre[kTile / 64];
+        load_tile(pre, st, sorted, g0, cnt, lane, p);
+        const int nk = store_tile_kept(tile, pre, tb, fp, lane);
+        kept += nk;
         __syncthreads();
-        for (int j = 0; j < cnt; ++j) {
+        for (int j = 0; j < nk; ++j) {
             const float4 s = tile[j];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -281,7 +288,7 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
         if (has[h] && per_target)
             per_target[perm[kb + lane + 64 * h] - d.pbase] = cntu[h];
         u += (unsigned long long)cntu[h];
-        c += act[h] ? (unsigned long long)total : 0ull;
+        c += act[h] ? (unsigned long long)kept : 0ull;
     }
     for (int o = 1; o < 64; o <<= 1) {
         u += __shfl_xor(u, o, 64);

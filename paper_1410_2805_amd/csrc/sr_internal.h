@@ -20,7 +20,7 @@ struct sr_ctx {
     int *status = nullptr;      // device status word (bit 0: bad coordinate)
     int64_t *stats = nullptr;   // device counters for sr_pair_stats
     std::string err;
-    int xsplit = 2;             // sub-cells per chaining cell along x in sr_force
+    int xsplit = 1;             // sub-cells per chaining cell along x in sr_force
     int order = 1;              // work-item order: 0 cell order, 1 cost buckets (LPT)
     int persistent = 0;         // 1: persistent workgroups pull items from a counter
     bool timing = false;        // record events around sr_force phases
@@ -57,6 +57,7 @@ struct Geom {
 constexpr int kSplitMaxCells = 1023;  // per axis, split coordinates
 
 constexpr int kMaxXsplit = 4;
+constexpr double kMaxSide = 131072.0;  // largest box side (padding lies far beyond)
 
 // One box of a batch.  Particles of all boxes are numbered consecutively
 // (box b owns [pbase, pbase + n)) and so are their cells ([cbase, cbase +

@@ -144,25 +144,6 @@ __device__ __forceinline__ bool is_passive(float4 p, const Geom &g)
     return pas;
 }
 
-// Stage sources [g0, g0 + cntp) of the stencil into the tile.
-__device__ __forceinline__ void stage_tile(float4 *tile, const Stencil &st,
-                                           const float4 *__restrict__ sorted, int g0, int cnt,
-                                           int cntp, int lane, int &p)
-{
-    for (int q = lane; q < cntp; q += 64) {
-        float4 v = make_float4(kFar, kFar, kFar, 0.f);
-        if (q < cnt) {
-            const int gi = g0 + q;
-            while (gi >= st.pbeg[p + 1])
-                ++p;
-            const float4 s = sorted[st.psrc[p] + (gi - st.pbeg[p])];
-            const float4 sh = st.psh[p];
-            v = make_float4(s.x + sh.x, s.y + sh.y, s.z + sh.z, s.w);
-        }
-        tile[q] = v;
-    }
-}
-
 // Loads sources [g0, g0 + cnt) of the stencil (cnt <= kTile) into registers,
 // entry q = lane + 64 k in pre[k]; entries past cnt are far, massless padding.
 __device__ __forceinline__ void load_tile(float4 (&pre)[kTile / 64], const Stencil &st,
@@ -183,6 +164,121 @@ __device__ __forceinline__ void load_tile(float4 (&pre)[kTile / 64], const Stenc
         }
         pre[k] = v;
     }
+}
+
+// Bounding box of a work item's targets, for a test that drops stencil
+// sources before the pair loop.  The paper's chaining mesh (Sec. 3.1) offers
+// every target all particles of its neighbour cells and lets the cutoff
+// reject the far ones; the test rejects, per item, sources that are beyond
+// the cutoff of the whole box, which changes no sum (see source_kept).
+struct TargetBox {
+    float lo[3], hi[3];
+};
+
+// One step of a row reduction: v combined with lane (ctrl) of its row.
+template <int kCtrl, bool kMax>
+__device__ __forceinline__ float row_step(float v)
+{
+    const float o = __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), kCtrl, 0xF, 0xF, false));
+    return kMax ? fmaxf(v, o) : fminf(v, o);
+}
+
+// Minimum (kMax false) or maximum of v over the 64 lanes, in a scalar
+// register: within each row of 16 lanes by exchanges across pairs, quads,
+// half rows and the row (DPP quad_perm [1,0,3,2], [2,3,0,1], row half
+// mirror, row mirror), then across the four rows' first lanes.
+template <bool kMax>
+__device__ __forceinline__ float wave_extreme(float v)
+{
+    v = row_step<0xB1, kMax>(v);
+    v = row_step<0x4E, kMax>(v);
+    v = row_step<0x141, kMax>(v);
+    v = row_step<0x140, kMax>(v);
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    const float m = kMax ? fmaxf(fmaxf(r0, r1), fmaxf(r2, r3)) : fminf(fminf(r0, r1), fminf(r2, r3));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));
+}
+
+// Every lane passes the two targets it holds (equal when it holds one); the
+// box comes back the same in all lanes.  All 64 lanes must be active.
+__device__ __forceinline__ TargetBox target_box(float xi, float yi, float zi, float xj, float yj,
+                                                float zj)
+{
+    TargetBox b;
+    b.lo[0] = wave_extreme<false>(fminf(xi, xj));
+    b.lo[1] = wave_extreme<false>(fminf(yi, yj));
+    b.lo[2] = wave_extreme<false>(fminf(zi, zj));
+    b.hi[0] = wave_extreme<true>(fmaxf(xi, xj));
+    b.hi[1] = wave_extreme<true>(fmaxf(yi, yj));
+    b.hi[2] = wave_extreme<true>(fmaxf(zi, zj));
+    return b;
+}
+
+// Whether source s can interact with any target in the box: its per-axis gap
+// g to the box is at most its distance along that axis to every target in
+// it (rounding is monotone), so g^2 summed by the pair loop's own FMA chain,
+// with eps, is at most every pair's se.  A source that fails se < rcut here
+// fails it for every target of the box: dropping it changes no result.
+__device__ __forceinline__ bool source_kept(const float4 &s, const TargetBox &b,
+                                            const ForceParams &fp)
+{
+    const float gx = fmaxf(0.f, fmaxf(b.lo[0] - s.x, s.x - b.hi[0]));
+    const float gy = fmaxf(0.f, fmaxf(b.lo[1] - s.y, s.y - b.hi[1]));
+    const float gz = fmaxf(0.f, fmaxf(b.lo[2] - s.z, s.z - b.hi[2]));
+    return fmaf(gx, gx, fmaf(gy, gy, fmaf(gz, gz, fp.eps))) < fp.rcut;
+}
+
+// Reciprocal of a tile quantum q (1 <= q <= 64) in 16-bit fixed point,
+// rounded up, for quanta_of; uniform across the wavefront.
+__device__ __forceinline__ int quantum_recip(int q)
+{
+    return __builtin_amdgcn_readfirstlane((65536 + q - 1) / q);
+}
+
+// ceil(n / q) for 0 <= n <= kTile from r = quantum_recip(q): with x = n + q - 1
+// < 320, x r / 2^16 exceeds x / q by less than 320 / 2^16 < 1 / 64 <= 1 / q,
+// which cannot reach the next integer.
+__device__ __forceinline__ int quanta_of(int n, int q, int r)
+{
+    return ((n + q - 1) * r) >> 16;
+}
+
+// Writes the kTile entries of a tile loaded by load_tile as a stable
+// partition: first those that pass source_kept against the box, in load
+// order (entry q = lane + 64 k), then all others.  Returns the count of
+// kept entries.  An entry that fails the box test fails the pair loop's
+// cutoff for every target in the box and adds exactly zero to it (as does
+// load_tile's far padding, which always fails), so any prefix of the tile
+// that covers the kept entries gives every target the same sum.
+__device__ __forceinline__ int store_tile_kept(float4 *tile, const float4 (&pre)[kTile / 64],
+                                               const TargetBox &box, const ForceParams &fp,
+                                               int lane)
+{
+    bool kk[kTile / 64];
+    unsigned long long bal[kTile / 64];
+    int base[kTile / 64];
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < kTile / 64; ++k) {
+        kk[k] = source_kept(pre[k], box, fp);
+        bal[k] = __ballot(kk[k]);
+        base[k] = n;
+        n += __popcll(bal[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kTile / 64; ++k) {
+        // kept entries before this one in load order
+        const int kp = base[k] + (int)__builtin_amdgcn_mbcnt_hi(
+                                     (unsigned)(bal[k] >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)bal[k], 0u));
+        const int q = lane + 64 * k;
+        tile[kk[k] ? kp : n + (q - kp)] = pre[k];
+    }
+    return n;
 }
 
 // One pair of Eq. (force) for one lane: source s, target (xi, yi, zi);

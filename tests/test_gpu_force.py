@@ -192,6 +192,8 @@ def test_invalid_args(sr, ctx, poly):
         sr.sr_force(ctx, *args, sr.Box.make(12.0), 3.0, 3.0, 0.0, poly)
     with pytest.raises(sr.SRError):  # periodic with fewer than 3 cells
         sr.sr_force(ctx, *args, sr.Box.make((12.0, 12.0, 5.0)), 2.5, 2.0, EPS, poly)
+    with pytest.raises(sr.SRError):  # a side beyond 131072
+        sr.sr_force(ctx, *args, sr.Box.make((262144.0, 12.0, 12.0)), 3.0, 3.0, EPS, poly)
 
 
 def test_pair_stats_match_oracle(sr, ctx, poly):
@@ -206,6 +208,36 @@ def test_pair_stats_match_oracle(sr, ctx, poly):
     assert np.array_equal(per[~tie], ref["npair"][~tie])
     assert abs(useful - int(ref["npair"].sum())) <= int(tie.sum()) * 2
     assert cand > useful
+
+
+def test_box_test_bounds_candidates(sr, ctx, poly):
+    """The work item's box test drops sources and keeps every interacting
+    pair: per-target counts still match the oracle exactly (previous test),
+    and the candidates lie between the useful pairs and the full 27-cell
+    count, which at one sub-cell per cell is the sum over targets of the
+    particle counts of the 27 cells around theirs (oracle binning)."""
+    p = W.uniform(20000, 24.0, 16)
+    t = to_dev(p)
+    box = sr.Box.make(p.L)
+    before = ctx.get_tuning()
+    try:
+        ctx.set_tuning(xsplit=1)
+        useful, cand, _ = sr.sr_pair_stats(ctx, t["x"], t["y"], t["z"], box, 3.0, R_MAX)
+    finally:
+        ctx.set_tuning(**before)
+    off, _, cid = O.bin(p.x, p.y, p.z, p.L, 3.0)
+    nc = 8
+    counts = np.diff(off).reshape(nc, nc, nc)  # [cz, cy, cx]
+    near = np.zeros_like(counts)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                near += np.roll(counts, (dz, dy, dx), axis=(0, 1, 2))
+    full = int(near.reshape(-1)[cid].sum())
+    assert useful < cand <= full
+    # a cell of ~39 targets spans most of the cell, so the box keeps about
+    # the cell's r_max neighbourhood: well under the 27-cell volume
+    assert cand < 0.85 * full, (cand, full)
 
 
 @pytest.mark.slow
