@@ -483,6 +483,16 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
     const bool work = __any((has_target && !pas) || (has2 && !pas2));
     const int quantum = 4 * S;
     const int cap = kTile / quantum * quantum;
+    const int qrecip = quantum_recip(quantum);
+    // the leaf's box holds every target of the chunk (it is the exact float
+    // min/max of the leaf's particles, and adding F is monotone): sources
+    // beyond the cutoff of all of it are dropped before the pair loop
+    TargetBox tb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        tb.lo[a] = tlo[a];
+        tb.hi[a] = thi[a];
+    }
     float acx = 0.f, acy = 0.f, acz = 0.f;
     float bcx = 0.f, bcy = 0.f, bcz = 0.f;
     int npiece = 0, total = 0;
@@ -498,17 +508,14 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
             int cnt = total < cap ? total : cap;
             load_tile(pre, st, sorted, g0, cnt, lane, p);
             for (;;) {
-                const int cntp = (cnt + quantum - 1) / quantum * quantum;
-#pragma unroll
-                for (int k = 0; k < kTile / 64; ++k)
-                    if (lane + 64 * k < cntp)
-                        tile[lane + 64 * k] = pre[k];
+                const int nq =
+                    quanta_of(store_tile_kept(tile, pre, tb, fp, lane), quantum, qrecip);
                 __syncthreads();
                 const int g1 = g0 + cnt;
                 const int cnt1 = total - g1 < cap ? total - g1 : cap;
                 if (cnt1 > 0)
                     load_tile(pre, st, sorted, g1, cnt1, lane, p);
-                const int slice = cntp / S;
+                const int slice = 4 * nq;
                 const float4 *src = tile + (has_target ? part : 0) * slice;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
                 if (two) {
