@@ -443,6 +443,51 @@ __global__ __launch_bounds__(256) void k_leaf_of(int n, const int *__restrict__ 
         leaf_of[perm[i]] = lscan[i] + flag[i] - 1;
 }
 
+// load_tile without the image shifts: entry q = lane + 64 k in pre[k]; entries past
+// cnt are far, massless padding.  Returns each entry's piece in byte k, for
+// shift_tile.  Nothing here reads the loaded values, so the loads stay in
+// flight (behind the previous tile's pair loop) until shift_tile.  This
+// holds the loads' registers longer: the tree pass, whose occupancy is set by
+// its interaction-list code, gains from it; the mesh pass would lose the
+// occupancy step it sits on and keeps load_tile (sr_pair.h).
+__device__ __forceinline__ unsigned load_tile_deferred(float4 (&pre)[kTile / 64],
+                                                       const Stencil &st,
+                                                       const float4 *__restrict__ sorted,
+                                                       int g0, int cnt, int lane, int &p)
+{
+    unsigned pk = 0u;
+#pragma unroll
+    for (int k = 0; k < kTile / 64; ++k) {
+        const int q = lane + 64 * k;
+        float4 v = make_float4(kFar, kFar, kFar, 0.f);
+        if (q < cnt) {
+            const int gi = g0 + q;
+            while (gi >= st.pbeg[p + 1])
+                ++p;
+            v = sorted[st.psrc[p] + (gi - st.pbeg[p])];
+            pk |= (unsigned)p << (8 * k);
+        }
+        pre[k] = v;
+    }
+    return pk;
+}
+
+// Adds the image shift of each entry's piece (kMaxPieces <= 256 fits a byte).
+// Padding entries carry piece 0, which exists whenever a tile is loaded; a
+// shift of at most one box side (<= 131072) leaves them far outside every
+// box.
+__device__ __forceinline__ void shift_tile(float4 (&pre)[kTile / 64], unsigned pk,
+                                           const Stencil &st)
+{
+#pragma unroll
+    for (int k = 0; k < kTile / 64; ++k) {
+        const float4 sh = st.psh[(pk >> (8 * k)) & 255u];
+        pre[k].x += sh.x;
+        pre[k].y += sh.y;
+        pre[k].z += sh.z;
+    }
+}
+
 // The pair loop of one leaf chunk (one wavefront; single-box batch).
 __device__ void process_leaf_item(const Batch &B, const int4 item,
                                   const float4 *__restrict__ sorted, const int *__restrict__ perm,
@@ -506,15 +551,16 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
             float4 pre[kTile / 64];
             int p = 0, g0 = 0;
             int cnt = total < cap ? total : cap;
-            load_tile(pre, st, sorted, g0, cnt, lane, p);
+            unsigned pk = load_tile_deferred(pre, st, sorted, g0, cnt, lane, p);
             for (;;) {
+                shift_tile(pre, pk, st);
                 const int nq =
                     quanta_of(store_tile_kept(tile, pre, tb, fp, lane), quantum, qrecip);
                 __syncthreads();
                 const int g1 = g0 + cnt;
                 const int cnt1 = total - g1 < cap ? total - g1 : cap;
                 if (cnt1 > 0)
-                    load_tile(pre, st, sorted, g1, cnt1, lane, p);
+                    pk = load_tile_deferred(pre, st, sorted, g1, cnt1, lane, p);
                 const int slice = 4 * nq;
                 const float4 *src = tile + (has_target ? part : 0) * slice;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
