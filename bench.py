@@ -376,6 +376,8 @@ def bench_step(args):
     del q, psi
     box = sr.Box.make(L)
     ctx = sr.Context(0, arena_bytes=sr.sr_scratch_bytes(box, cell, n, True))
+    if args.xsplit:
+        ctx.set_tuning(xsplit=args.xsplit)
     x, y, z = [torch.from_numpy(np.ascontiguousarray(pos[:, d])).to(dev) for d in range(3)]
     c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x, y, z, box, cell)
     del x, y, z
@@ -500,6 +502,8 @@ def bench_step_ml(args):
     box = sr.Box.make(L)
     n = 128 ** 3
     ctx = sr.Context(0, arena_bytes=sr.sr_scratch_bytes(box, cell, n, True) + 3 * n + 2 ** 22)
+    if args.xsplit:
+        ctx.set_tuning(xsplit=args.xsplit)
     pm = sr.PM(ctx, ng, L)
     reps = max(2, min(args.steps, 8))
 
