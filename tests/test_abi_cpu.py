@@ -40,6 +40,21 @@ def test_grid_dims_and_scratch():
     b1 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, True)
     b0 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, False)
     assert b1 > b0 > 2 ** 21 * 8
+    # box sides are bounded so that tile padding (at 1e6) stays beyond every cutoff
+    assert sr.sr_scratch_bytes(sr.Box.make((131072.0, 12.0, 12.0)), 3.0, 1000, True) > 0
+    with pytest.raises(sr.SRError):
+        sr.sr_scratch_bytes(sr.Box.make((131073.0, 12.0, 12.0)), 3.0, 1000, True)
+
+
+def test_quanta_fixed_point_rounding():
+    """The pair loop rounds a tile's kept count n (0..256) up to a multiple
+    of the slice quantum q = 4 S (S = 1..16) with a 16-bit fixed-point
+    reciprocal r = ceil(2^16 / q): ((n + q - 1) r) >> 16 = ceil(n / q) over
+    every q up to 64 (quanta_of in sr_pair.h)."""
+    for q in range(1, 65):
+        r = (65536 + q - 1) // q
+        for n in range(0, 257):
+            assert ((n + q - 1) * r) >> 16 == -(-n // q), (n, q)
 
 
 def test_null_context_is_rejected():
