@@ -175,32 +175,40 @@ struct TargetBox {
     float lo[3], hi[3];
 };
 
-// One step of a row reduction: v combined with lane (ctrl) of its row.
-template <int kCtrl, bool kMax>
-__device__ __forceinline__ float row_step(float v)
+// Order-preserving map between finite float bit patterns and int32 (its own
+// inverse): non-negative values keep their bits, negative ones have the
+// magnitude bits flipped, so integer order is float order (-0 below +0).
+__device__ __forceinline__ int ordered_key(int b)
 {
-    const float o = __int_as_float(
-        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), kCtrl, 0xF, 0xF, false));
-    return kMax ? fmaxf(v, o) : fminf(v, o);
+    return b ^ ((b >> 31) & 0x7fffffff);
 }
 
-// Minimum (kMax false) or maximum of v over the 64 lanes, in a scalar
-// register: within each row of 16 lanes by exchanges across pairs, quads,
-// half rows and the row (DPP quad_perm [1,0,3,2], [2,3,0,1], row half
+// One step of a row reduction: v combined with lane (ctrl) of its row.
+template <int kCtrl, bool kMax>
+__device__ __forceinline__ int row_step(int v)
+{
+    const int o = __builtin_amdgcn_mov_dpp(v, kCtrl, 0xF, 0xF, true);
+    return kMax ? max(v, o) : min(v, o);
+}
+
+// Minimum (kMax false) or maximum of a and b over the 64 lanes, uniform: on
+// ordered keys, within each row of 16 lanes by exchanges across pairs,
+// quads, half rows and the row (DPP quad_perm [1,0,3,2], [2,3,0,1], row half
 // mirror, row mirror), then across the four rows' first lanes.
 template <bool kMax>
-__device__ __forceinline__ float wave_extreme(float v)
+__device__ __forceinline__ float wave_extreme(float a, float b)
 {
+    const int ka = ordered_key(__float_as_int(a)), kb = ordered_key(__float_as_int(b));
+    int v = kMax ? max(ka, kb) : min(ka, kb);
     v = row_step<0xB1, kMax>(v);
     v = row_step<0x4E, kMax>(v);
     v = row_step<0x141, kMax>(v);
     v = row_step<0x140, kMax>(v);
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-    const float m = kMax ? fmaxf(fmaxf(r0, r1), fmaxf(r2, r3)) : fminf(fminf(r0, r1), fminf(r2, r3));
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    const int m = kMax ? max(max(r0, r1), max(r2, r3)) : min(min(r0, r1), min(r2, r3));
+    // held in a scalar register through the whole item
+    return __int_as_float(ordered_key(__builtin_amdgcn_readfirstlane(m)));
 }
 
 // Every lane passes the two targets it holds (equal when it holds one); the
@@ -209,12 +217,12 @@ __device__ __forceinline__ TargetBox target_box(float xi, float yi, float zi, fl
                                                 float zj)
 {
     TargetBox b;
-    b.lo[0] = wave_extreme<false>(fminf(xi, xj));
-    b.lo[1] = wave_extreme<false>(fminf(yi, yj));
-    b.lo[2] = wave_extreme<false>(fminf(zi, zj));
-    b.hi[0] = wave_extreme<true>(fmaxf(xi, xj));
-    b.hi[1] = wave_extreme<true>(fmaxf(yi, yj));
-    b.hi[2] = wave_extreme<true>(fmaxf(zi, zj));
+    b.lo[0] = wave_extreme<false>(xi, xj);
+    b.lo[1] = wave_extreme<false>(yi, yj);
+    b.lo[2] = wave_extreme<false>(zi, zj);
+    b.hi[0] = wave_extreme<true>(xi, xj);
+    b.hi[1] = wave_extreme<true>(yi, yj);
+    b.hi[2] = wave_extreme<true>(zi, zj);
     return b;
 }
 
