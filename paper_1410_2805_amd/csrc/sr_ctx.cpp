@@ -81,6 +81,8 @@ int sr_make_geom(sr_ctx *ctx, const sr_box *box, double cell, Geom *g, int xspli
                            box->len[d]);
     }
     g->ncell = (int)nc;
+    div_const((unsigned)(g->nc[0] * g->nc[1]), &g->div_m[0], &g->div_s[0]);
+    div_const((unsigned)g->nc[0], &g->div_m[1], &g->div_s[1]);
     g->split = 0;
     g->periodic = box->periodic ? 1 : 0;
     g->skin = box->periodic ? 0.0 : box->skin;

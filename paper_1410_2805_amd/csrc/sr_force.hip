@@ -57,7 +57,7 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
     // two targets per lane: lane t of a group holds targets t and t + ln
     const bool two = item_two(item);
     const int ln = two ? (nt + 1) >> 1 : nt;
-    const int part = lane / ln;
+    const int part = lane_group(lane, ln);
     const int t = lane - part * ln;
     const bool has_target = part < S;
     const bool has2 = two && has_target && t + ln < nt;
@@ -78,8 +78,8 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
         // that padding stays inside the tile); the next pass's global loads
         // are issued before the current pass computes
         const int quantum = 4 * S;
-        const int cap = kTile / quantum * quantum;
-        const int qrecip = quantum_recip(quantum);
+        const int cap = kItemTab.cap[S];
+        const int qrecip = kItemTab.qrecip[S];
         // sources outside the cutoff of the whole box of the item's targets
         // are dropped before they reach the tile
         const TargetBox tb = target_box(xi, yi, zi, xj, yj, zj);

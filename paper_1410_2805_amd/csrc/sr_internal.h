@@ -52,7 +52,28 @@ struct Geom {
     int hx;
     int split;
     double skin;
+    // cell / (nc[0] nc[1]) and rem / nc[0] by multiply and shift (div_const)
+    unsigned div_m[2];
+    int div_s[2];
 };
+
+// Constants for the exact quotient n / d of any 0 <= n < 2^31 by a fixed
+// d >= 1 (Granlund and Montgomery's method): with s = ceil(log2 d) and
+// m = floor(2^(31+s) / d) + 1 < 2^32, n m / 2^(31+s) exceeds n / d by less
+// than n / 2^(31+s) < 2^-s <= 1 / d, so its floor is floor(n / d).
+inline void div_const(unsigned d, unsigned *m, int *s)
+{
+    int l = 0;
+    while ((1ull << l) < d)
+        ++l;
+    *s = l;
+    *m = (unsigned)(((1ull << (31 + l)) / d) + 1ull);
+}
+
+__host__ __device__ inline int div_by(int n, unsigned m, int s)
+{
+    return (int)(((unsigned long long)(unsigned)n * m) >> (31 + s));
+}
 
 constexpr int kSplitMaxCells = 1023;  // per axis, split coordinates
 

@@ -126,9 +126,9 @@ __device__ __forceinline__ void frame_shift(const Geom &g, const int cc[3], floa
 __device__ __forceinline__ void decode_cell(int cell, const Geom &g, int &cx, int &cy, int &cz)
 {
     const int plane = g.nc[0] * g.nc[1];
-    cz = cell / plane;
+    cz = div_by(cell, g.div_m[0], g.div_s[0]);
     const int rem = cell - cz * plane;
-    cy = rem / g.nc[0];
+    cy = div_by(rem, g.div_m[1], g.div_s[1]);
     cx = rem - cy * g.nc[0];
 }
 
@@ -240,14 +240,41 @@ __device__ __forceinline__ bool source_kept(const float4 &s, const TargetBox &b,
     return fmaf(gx, gx, fmaf(gy, gy, fmaf(gz, gz, fp.eps))) < fp.rcut;
 }
 
-// Reciprocal of a tile quantum q (1 <= q <= 64) in 16-bit fixed point,
-// rounded up, for quanta_of; uniform across the wavefront.
-__device__ __forceinline__ int quantum_recip(int q)
+// Per lane-group count S (1..16) of an item: the tile capacity cap[S] (a
+// multiple of the slice quantum 4 S) and the quantum's 16-bit fixed-point
+// reciprocal qrecip[S], rounded up, for quanta_of; per target count ln
+// (1..64) of a group, lnrecip[ln] = ceil(2^16 / ln), for lane_group.  Read
+// with a uniform index, so from scalar memory instead of dividing.
+struct ItemTables {
+    int cap[kMaxSplit + 1];
+    int qrecip[kMaxSplit + 1];
+    int lnrecip[65];
+};
+
+constexpr ItemTables make_item_tables()
 {
-    return __builtin_amdgcn_readfirstlane((65536 + q - 1) / q);
+    ItemTables t{};
+    for (int s = 1; s <= kMaxSplit; ++s) {
+        const int q = 4 * s;
+        t.cap[s] = kTile / q * q;
+        t.qrecip[s] = (65536 + q - 1) / q;
+    }
+    for (int l = 1; l <= 64; ++l)
+        t.lnrecip[l] = (65536 + l - 1) / l;
+    return t;
 }
 
-// ceil(n / q) for 0 <= n <= kTile from r = quantum_recip(q): with x = n + q - 1
+__constant__ const ItemTables kItemTab = make_item_tables();
+
+// lane / ln for lane < 64 and 1 <= ln <= 64: lane r / 2^16 exceeds lane / ln
+// by less than 64 / 2^16 < 1 / 64 <= 1 / ln, which cannot reach the next
+// integer.
+__device__ __forceinline__ int lane_group(int lane, int ln)
+{
+    return (lane * kItemTab.lnrecip[ln]) >> 16;
+}
+
+// ceil(n / q) for 0 <= n <= kTile from r = ceil(2^16 / q) (qrecip): with x = n + q - 1
 // < 320, x r / 2^16 exceeds x / q by less than 320 / 2^16 < 1 / 64 <= 1 / q,
 // which cannot reach the next integer.
 __device__ __forceinline__ int quanta_of(int n, int q, int r)

@@ -514,7 +514,7 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
     // two targets per lane: lane t of a group holds targets t and t + ln
     const bool two = item_two(item);
     const int ln = two ? (nt + 1) >> 1 : nt;
-    const int part = lane / ln;
+    const int part = lane_group(lane, ln);
     const int t = lane - part * ln;
     const bool has_target = part < S;
     const bool has2 = two && has_target && t + ln < nt;
@@ -527,8 +527,8 @@ __device__ void process_leaf_item(const Batch &B, const int4 item,
     const bool uniform = mass_mixed[0] == 0;
     const bool work = __any((has_target && !pas) || (has2 && !pas2));
     const int quantum = 4 * S;
-    const int cap = kTile / quantum * quantum;
-    const int qrecip = quantum_recip(quantum);
+    const int cap = kItemTab.cap[S];
+    const int qrecip = kItemTab.qrecip[S];
     // the leaf's box holds every target of the chunk (it is the exact float
     // min/max of the leaf's particles, and adding F is monotone): sources
     // beyond the cutoff of all of it are dropped before the pair loop

@@ -62,3 +62,35 @@ def test_null_context_is_rejected():
     assert sr.lib.sr_sync(None) == sr.SR_EINVAL
     assert sr.lib.sr_ctx_destroy(None) == sr.SR_EINVAL
     assert sr.lib.sr_bin(None, None, None, None, 0, None, 3.0, None, None) == sr.SR_EINVAL
+
+
+def test_lane_group_fixed_point_division():
+    """lane // ln from a 16-bit fixed-point reciprocal, for every lane of a
+    wavefront and every lane-group length (lane_group in sr_pair.h)."""
+    for ln in range(1, 65):
+        r = (65536 + ln - 1) // ln
+        for lane in range(64):
+            assert (lane * r) >> 16 == lane // ln, (lane, ln)
+
+
+def test_cell_decode_division_constants():
+    """Cell decoding divides by nc[0] nc[1] and nc[0] with multiply-shift
+    constants (div_const in sr_internal.h): s = ceil(log2 d), m =
+    floor(2^(31+s) / d) + 1 must fit 32 bits and give floor(n / d) for all
+    0 <= n < 2^31."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    divisors = list(range(1, 5000)) + [2 ** k for k in range(31)] + \
+        [2 ** k + 1 for k in range(1, 31)] + [2 ** k - 1 for k in range(2, 31)] + \
+        [int(v) for v in rng.integers(1, 2 ** 31 - 1, 2000)]
+    for d in divisors:
+        s = 0
+        while (1 << s) < d:
+            s += 1
+        m = (1 << (31 + s)) // d + 1
+        assert m < 2 ** 32, d
+        ns = [0, 1, d - 1, d, d + 1, 2 ** 31 - 1, 2 ** 31 - 2, (2 ** 31 - 1) // d * d,
+              (2 ** 31 - 1) // d * d - 1] + [int(v) for v in rng.integers(0, 2 ** 31, 64)]
+        for n in ns:
+            if 0 <= n < 2 ** 31:
+                assert (n * m) >> (31 + s) == n // d, (n, d)
