@@ -467,8 +467,11 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
 
 // Block-level sort of one large cell: LDS-sorted runs of kLargeCell, then
 // merge rounds in which every element finds its output slot from its rank in
-// the partner run (values are distinct original indices).
-__global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
+// the partner run (values are distinct original indices).  The rank is a
+// binary search in global memory, a chain of dependent loads; the block is
+// kLargeBlock threads wide so that more of them are in flight per round.
+constexpr int kLargeBlock = 1024;
+__global__ __launch_bounds__(kLargeBlock) void k_segsort_large(Batch B,
                                                           const int *__restrict__ offsets,
                                                           int *__restrict__ perm,
                                                           int *__restrict__ tmp,
@@ -485,12 +488,12 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
         // 1) sort runs of kLargeCell in LDS (bitonic, whole block)
         for (int r0 = 0; r0 < len; r0 += kLargeCell) {
             int rl = len - r0 < kLargeCell ? len - r0 : kLargeCell;
-            for (int t = threadIdx.x; t < kLargeCell; t += kBlock)
+            for (int t = threadIdx.x; t < kLargeCell; t += kLargeBlock)
                 buf[t] = t < rl ? perm[b + r0 + t] : INT_MAX;
             __syncthreads();
             for (int k = 2; k <= kLargeCell; k <<= 1) {
                 for (int j = k >> 1; j > 0; j >>= 1) {
-                    for (int t = threadIdx.x; t < kLargeCell / 2; t += kBlock) {
+                    for (int t = threadIdx.x; t < kLargeCell / 2; t += kLargeBlock) {
                         int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
                         int l = i + j;
                         bool up = (i & k) == 0;
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
                     __syncthreads();
                 }
             }
-            for (int t = threadIdx.x; t < rl; t += kBlock)
+            for (int t = threadIdx.x; t < rl; t += kLargeBlock)
                 perm[b + r0 + t] = buf[t];
             __syncthreads();
         }
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
         int *src = perm + b;
         int *dst = tmp + b;
         for (int w = kLargeCell; w < len; w <<= 1) {
-            for (int e = threadIdx.x; e < len; e += kBlock) {
+            for (int e = threadIdx.x; e < len; e += kLargeBlock) {
                 int pair0 = (e / (2 * w)) * (2 * w);
                 int mid = pair0 + w;              // start of the right run
                 int end = pair0 + 2 * w < len ? pair0 + 2 * w : len;
@@ -542,12 +545,12 @@ __global__ __launch_bounds__(kBlock) void k_segsort_large(Batch B,
             dst = t;
         }
         if (src != perm + b) {
-            for (int e = threadIdx.x; e < len; e += kBlock)
+            for (int e = threadIdx.x; e < len; e += kLargeBlock)
                 perm[b + e] = src[e];
             __syncthreads();
         }
         if (inv) {
-            for (int e = threadIdx.x; e < len; e += kBlock)
+            for (int e = threadIdx.x; e < len; e += kLargeBlock)
                 inv[perm[b + e]] = b + e;
         }
         __syncthreads();
@@ -685,9 +688,9 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
         return rc;
     if (n > kLargeCell) {
         int max_large = n / (kLargeCell + 1) + 1;
-        int grid = max_large < 2048 ? max_large : 2048;
-        hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kBlock), 0, ctx->stream, B, offsets,
-                           perm, s.tmp, s.large_list, s.large_count, inv);
+        int grid = max_large < 512 ? max_large : 512;
+        hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kLargeBlock), 0, ctx->stream, B,
+                           offsets, perm, s.tmp, s.large_list, s.large_count, inv);
         if ((rc = sr_check_launch(ctx, "k_segsort_large")))
             return rc;
     }
