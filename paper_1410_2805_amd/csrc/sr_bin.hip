@@ -471,6 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
 // binary search in global memory, a chain of dependent loads; the block is
 // kLargeBlock threads wide so that more of them are in flight per round.
 constexpr int kLargeBlock = 1024;
+constexpr int kMergeIlp = 4;
 __global__ __launch_bounds__(kLargeBlock) void k_segsort_large(Batch B,
                                                           const int *__restrict__ offsets,
                                                           int *__restrict__ perm,
@@ -514,30 +515,55 @@ __global__ __launch_bounds__(kLargeBlock) void k_segsort_large(Batch B,
         int *src = perm + b;
         int *dst = tmp + b;
         for (int w = kLargeCell; w < len; w <<= 1) {
-            for (int e = threadIdx.x; e < len; e += kLargeBlock) {
-                int pair0 = (e / (2 * w)) * (2 * w);
-                int mid = pair0 + w;              // start of the right run
-                int end = pair0 + 2 * w < len ? pair0 + 2 * w : len;
-                int v = src[e];
-                int lo, hi;
-                if (e < mid) {  // left element: count right elements < v
-                    lo = mid;
-                    hi = end;
-                } else {        // right element: count left elements < v
-                    lo = pair0;
-                    hi = mid;
+            // kMergeIlp elements per thread; each search step loads for all of
+            // them before comparing, so the loads are in flight together
+            for (int e0 = threadIdx.x; e0 < len; e0 += kMergeIlp * kLargeBlock) {
+                int v[kMergeIlp], lo[kMergeIlp], base[kMergeIlp], cnt[kMergeIlp];
+                int at[kMergeIlp];
+#pragma unroll
+                for (int k = 0; k < kMergeIlp; ++k) {
+                    const int e = e0 + k * kLargeBlock;
+                    cnt[k] = 0;
+                    at[k] = -1;
+                    v[k] = 0;
+                    lo[k] = 0;
+                    base[k] = 0;
+                    if (e < len) {
+                        const int pair0 = (e / (2 * w)) * (2 * w);
+                        const int mid = pair0 + w;  // start of the right run
+                        const int end = pair0 + 2 * w < len ? pair0 + 2 * w : len;
+                        v[k] = src[e];
+                        // left element: count right elements < v, and back
+                        const int l = e < mid ? mid : pair0, h = e < mid ? end : mid;
+                        lo[k] = l;
+                        base[k] = l;
+                        cnt[k] = h > l ? h - l : 0;
+                        at[k] = pair0 + (e < mid ? e - pair0 : e - mid);
+                    }
                 }
-                int a = lo, c = hi;
-                while (a < c) {
-                    int h = (a + c) >> 1;
-                    if (src[h] < v)
-                        a = h + 1;
-                    else
-                        c = h;
+                for (;;) {
+                    int x[kMergeIlp];
+                    bool more = false;
+#pragma unroll
+                    for (int k = 0; k < kMergeIlp; ++k) {
+                        // a finished search reads slot 0 of the cell (in range)
+                        x[k] = src[cnt[k] > 0 ? base[k] + (cnt[k] >> 1) : 0];
+                        more = more || cnt[k] > 0;
+                    }
+                    if (!more)
+                        break;
+#pragma unroll
+                    for (int k = 0; k < kMergeIlp; ++k) {
+                        const int half = cnt[k] >> 1;
+                        const bool right = cnt[k] > 0 && x[k] < v[k];
+                        base[k] = right ? base[k] + half + 1 : base[k];
+                        cnt[k] = cnt[k] > 0 ? (right ? cnt[k] - half - 1 : half) : 0;
+                    }
                 }
-                int rank_other = a - lo;
-                int own = (e < mid) ? e - pair0 : e - mid;
-                dst[pair0 + own + rank_other] = v;
+#pragma unroll
+                for (int k = 0; k < kMergeIlp; ++k)
+                    if (at[k] >= 0)
+                        dst[at[k] + (base[k] - lo[k])] = v[k];
             }
             __syncthreads();
             int *t = src;
