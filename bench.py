@@ -683,7 +683,8 @@ def bench_serving(args):
             log("  %d/%d" % (k + 1, len(sizes)))
             t0 = time.perf_counter()
     ctx = sr.Context(0)
-    srv = sr.Server(ctx, 64 << 30, 64, R_MAX, EPS, poly, 3.0)
+    srv = sr.Server(ctx, 64 << 30, 64, R_MAX, EPS, poly, 3.0,
+                    **({"xsplit": args.xsplit} if args.xsplit else {}))
     # warm-up request (compilation, allocator)
     warm = workloads.serving_trace(4, rate=1000.0, seed=99, ng_lo=24, ng_hi=32)
     serving.run_server(srv, warm, boxes)
