@@ -240,6 +240,53 @@ def test_box_test_bounds_candidates(sr, ctx, poly):
     assert cand < 0.85 * full, (cand, full)
 
 
+def _se32(xi, yi, zi, xj, yj, zj):
+    """The pair loop's squared separation with eps = 0, fma(dx,dx, fma(dy,dy,
+    fma(dz,dz, 0))) in float32: each product and sum below is exact in float64
+    for these inputs, then rounded once, as an FMA does."""
+    f32 = np.float32
+    dx = np.float64(f32(f32(xj) - f32(xi)))
+    dy = np.float64(f32(f32(yj) - f32(yi)))
+    dz = np.float64(f32(f32(zj) - f32(zi)))
+    t = np.float64(f32(dz * dz))
+    t = np.float64(f32(dy * dy + t))
+    return f32(dx * dx + t)
+
+
+def test_box_test_keeps_pairs_at_the_cutoff(sr, ctx):
+    """Sources one float below, at and one float above the cutoff from the
+    box of a cell's targets, along x and across x and y: the per-particle
+    pair counts (with the box test) equal a float32 brute force exactly."""
+    f32 = np.float32
+    below = float(np.nextafter(f32(14.0), f32(0.0)))
+    above = float(np.nextafter(f32(14.0), f32(20.0)))
+    pts = [(10.0, 10.5, 10.5), (11.0, 10.5, 10.5), (10.25, 10.5, 10.5),   # targets of one cell
+           (below, 10.5, 10.5), (14.0, 10.5, 10.5), (above, 10.5, 10.5),  # x gap 3 - ulp, 3, 3 + ulp
+           (7.0, 10.5, 10.5), (float(np.nextafter(f32(7.0), f32(8.0))), 10.5, 10.5),
+           (11.0, 13.5, 10.5), (11.0, float(np.nextafter(f32(13.5), f32(0.0))), 10.5),
+           (13.25, 12.25, 10.5), (13.0, 12.5, 10.5)]                      # x and y: 2.25^2 + 1.75^2 < 9
+    x, y, z = (np.array([p[d] for p in pts], dtype=np.float32) for d in range(3))
+    n = len(pts)
+    want = np.zeros(n, dtype=np.int64)
+    r2 = f32(R_MAX * R_MAX)
+    for i in range(n):
+        for j in range(n):
+            if i != j and _se32(x[i], y[i], z[i], x[j], y[j], z[j]) < r2:
+                want[i] += 1
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(a).to(dev) for a in (x, y, z)]
+    box = sr.Box.make(24.0)
+    for xs in (1, 2):
+        before = ctx.get_tuning()
+        try:
+            ctx.set_tuning(xsplit=xs)
+            useful, cand, per = sr.sr_pair_stats(ctx, *t, box, 3.0, R_MAX, per_target=True)
+        finally:
+            ctx.set_tuning(**before)
+        assert np.array_equal(per.cpu().numpy(), want), (xs, per.cpu().numpy(), want)
+        assert useful == int(want.sum()) and cand >= useful
+
+
 @pytest.mark.slow
 def test_zeldovich_128_sampled(sr, ctx, poly):
     """Full 128^3 Zel'dovich box as timed by the benchmark, checked on a seeded
