@@ -75,8 +75,10 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
     if (__any((has_target && !pas) || (has2 && !pas2))) {
         const int total = st.pbeg[kMaxPieces];
         // a pass stages `cap` sources (a multiple of the 4 S slice quantum, so
-        // that padding stays inside the tile); the next pass's global loads
-        // are issued before the current pass computes
+        // that padding stays inside the tile); the next pass's sources are
+        // loaded before the current pass computes (each load waits for its
+        // image shift: deferring the shifts past the pair loop costs this
+        // kernel its occupancy step)
         const int quantum = 4 * S;
         const int cap = kItemTab.cap[S];
         const int qrecip = kItemTab.qrecip[S];
