@@ -94,3 +94,24 @@ def test_cell_decode_division_constants():
         for n in ns:
             if 0 <= n < 2 ** 31:
                 assert (n * m) >> (31 + s) == n // d, (n, d)
+
+
+def test_ordered_key_preserves_float_order():
+    """The target box is reduced on int32 keys b ^ ((b >> 31) & 0x7fffffff) of
+    the float bits b (ordered_key in sr_pair.h): integer order must be float
+    order over finite floats of both signs, and the map its own inverse."""
+    import numpy as np
+    rng = np.random.default_rng(11)
+    f = np.concatenate([rng.uniform(-300.0, 300.0, 20000), rng.normal(0.0, 1e-3, 5000),
+                        [0.0, -0.0, 1e-45, -1e-45, 131072.0, -131072.0, 3.4e38, -3.4e38]])
+    f = f.astype(np.float32)
+    b = f.view(np.int32)
+    key = b ^ ((b >> 31) & np.int32(0x7fffffff))
+    order = np.argsort(f, kind="stable")
+    fs, ks = f[order], key[order]
+    # wherever the floats increase the keys increase (only -0 and +0 tie
+    # as floats; their keys are -1 and 0)
+    strict = np.diff(fs) > 0
+    assert np.all(np.diff(ks.astype(np.int64))[strict] > 0)
+    back = key ^ ((key >> 31) & np.int32(0x7fffffff))
+    assert np.array_equal(back, b)
