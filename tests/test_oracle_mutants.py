@@ -33,6 +33,9 @@ MUTANTS = [
      "for (int64_t i = n - 1; i >= 0; --i)\n        perm[count[id[i]]++] = (int32_t)i;"),
     ("passive not strict", "if (lo < skin || hi < skin)", "if (lo <= skin || hi <= skin)"),
     ("kick before stream", "V[d][i] += dt * a[d * n + i];", "V[d][i] += 0.5 * dt * a[d * n + i];"),
+    ("abs sum without |d|", "double mag = fabs(w) * sqrt(s);", "double mag = fabs(w);"),
+    ("tie band too wide", "const double band = r2 * ldexp(1.0, -18);",
+     "const double band = r2 * ldexp(1.0, -8);"),
 ]
 
 PINS = [
@@ -48,6 +51,9 @@ PINS = [
     P.test_bin_exact_cell_edges,
     P.test_sks_free_streaming_and_reversibility,
     P.test_sks_one_step_closed_form,
+    lambda: [P.test_abs_sum_two_particles_closed_form(r, mj) for r, mj in ((0.5, 2.0), (2.9, 4.0))],
+    P.test_abs_sum_three_particles_closed_form,
+    lambda: [P.test_tie_band_membership(s) for s in (-1.0, 1.0)],
 ]
 
 

@@ -293,3 +293,73 @@ def test_sks_one_step_closed_form():
     assert v1[0, 0] == pytest.approx(dt * 3.0 / r ** 2, rel=1e-12)
     assert p1[0, 0] == pytest.approx(5.0 + 0.5 * dt * dt * 3.0 / r ** 2, rel=1e-14)
     assert np.all(v1[:, 1:] == 0) and np.all(p1[:, 1:] == pos[:, 1:])
+
+
+def _on_axis(sources, L=64.0, eps=1e-22, poly=ZERO):
+    """Target at the box centre, sources at signed distances along x with the
+    given masses: [(distance, mass), ...].  Returns the oracle's result for
+    the target."""
+    c = L / 2
+    x = np.array([c] + [c + d for d, _ in sources])
+    y = np.full(x.shape, c)
+    m = np.array([1.0] + [mj for _, mj in sources])
+    return O.force(x, y, y, m, L, 3.0, eps, poly, targets=[0])
+
+
+@pytest.mark.parametrize("r,mj", [(0.05, 1.0), (0.5, 2.0), (1.7, 0.25), (2.9, 4.0)])
+def test_abs_sum_two_particles_closed_form(r, mj):
+    """S_i, the per-target sum of absolute pair terms, for one source: with
+    p = 0 and eps -> 0 it is Newton's m / r^2 (Sec. 2.6, G = 1), and with
+    eps = 0.1 the Plummer magnitude m r / (r^2 + eps)^(3/2).  One pair has
+    S_i = |a_i|."""
+    res = _on_axis([(r, mj)])
+    assert res["S"][0] == pytest.approx(mj / r ** 2, rel=1e-12)
+    assert res["S"][0] == pytest.approx(np.linalg.norm(res["a"][0]), rel=1e-14)
+    res = _on_axis([(-r, mj)], eps=0.1)
+    assert res["S"][0] == pytest.approx(mj * r / (r * r + 0.1) ** 1.5, rel=1e-12)
+
+
+def test_abs_sum_three_particles_closed_form():
+    """Two sources on opposite sides: the accelerations cancel or partly
+    cancel, S_i still adds both magnitudes; a source beyond r_max adds to
+    neither."""
+    res = _on_axis([(1.5, 2.0), (-1.5, 2.0)])
+    assert np.all(np.abs(res["a"][0]) < 1e-14)
+    assert res["S"][0] == pytest.approx(2 * 2.0 / 1.5 ** 2, rel=1e-12)
+    res = _on_axis([(0.8, 1.0), (-2.2, 3.0), (3.3, 5.0)])
+    want_s = 1.0 / 0.8 ** 2 + 3.0 / 2.2 ** 2
+    want_a = 1.0 / 0.8 ** 2 - 3.0 / 2.2 ** 2
+    assert res["npair"][0] == 2
+    assert res["S"][0] == pytest.approx(want_s, rel=1e-12)
+    assert res["a"][0][0] == pytest.approx(want_a, rel=1e-12)
+    # a fitted polynomial changes the terms, not the rule: S_i = sum of the
+    # two one-source magnitudes
+    c = gridfit.poly_coeffs().astype(np.float64)
+    both = _on_axis([(0.8, 1.0), (-2.2, 3.0)], eps=0.1, poly=c)
+    one = _on_axis([(0.8, 1.0)], eps=0.1, poly=c)
+    two = _on_axis([(-2.2, 3.0)], eps=0.1, poly=c)
+    assert both["S"][0] == pytest.approx(np.linalg.norm(one["a"][0]) + np.linalg.norm(two["a"][0]),
+                                         rel=1e-13)
+
+
+@pytest.mark.parametrize("sign", [-1.0, 1.0])
+def test_tie_band_membership(sign):
+    """A_i collects the pairs whose exact s lies within 2^-18 r_max^2 of the
+    cutoff on either side (pairs a float32 s may classify the other way):
+    s = r_max^2 (1 +- 2^-19) is in the band, s = r_max^2 (1 +- 2^-17) is not.
+    Its value is the pair's magnitude, m / r^2 for p = 0, eps -> 0."""
+    rin = 3.0 * np.sqrt(1.0 + sign * 2.0 ** -19)
+    rout = 3.0 * np.sqrt(1.0 + sign * 2.0 ** -17)
+    res = _on_axis([(rin, 2.0)])
+    assert res["A"][0] == pytest.approx(2.0 / rin ** 2, rel=1e-10)
+    assert res["npair"][0] == (1 if sign < 0 else 0)
+    if sign > 0:
+        assert np.all(res["a"][0] == 0.0) and res["S"][0] == 0.0
+    else:
+        assert res["S"][0] == pytest.approx(res["A"][0], rel=1e-14)
+    res = _on_axis([(-rout, 2.0)])
+    assert res["A"][0] == 0.0
+    assert res["npair"][0] == (1 if sign < 0 else 0)
+    # only the tie pair contributes to A_i when a near pair is present too
+    res = _on_axis([(rin, 2.0), (-0.5, 1.0), (1.0, 1.0)])
+    assert res["A"][0] == pytest.approx(2.0 / rin ** 2, rel=1e-10)
