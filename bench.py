@@ -1,10 +1,12 @@
 """Benchmark of the short-range particle-particle force on one MI355X.
 
-One step = one sr_force call on a resident synthetic box: binning into the
-chaining mesh (cell ids, histogram, scan, scatter, per-cell sort, gather),
-work-item construction, the pair loop over the 27-cell stencil, the
-scatter of accelerations back to the caller's order, and the FP64 momentum
-reduction.  Inputs are in HBM before the timed region starts.
+Default line: the 256^3 clustered open share (one GPU's share of a large run,
+70 % of the particles in NFW halos, a passive skin of 3 units).  One step =
+one sr_force call on the resident box: binning into the chaining mesh (cell
+ids, histogram, scan, scatter, per-cell sort, gather), work items, the pair
+loop over the 27-cell stencil, the scatter of accelerations back to the
+caller's order, and the FP64 momentum reduction.  Inputs are in HBM before
+the timed region starts.
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value     useful directed pair interactions per second of whole steps
@@ -13,6 +15,9 @@ Prints ONE JSON line on stdout (progress goes to stderr):
             from HIP events recorded on the library's stream
   cpu_baseline  the FP64 brute-force oracle on a bounded sample of targets
             of the same box, on this host's cores
+  accuracy  the timed result against the oracle on those targets
+  config    also carries the 128^3 Zel'dovich box (the same measurement),
+            the batched form (64 boxes) and the serving form (Poisson trace)
 """
 from __future__ import annotations
 
@@ -29,6 +34,7 @@ if ROOT not in sys.path:
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
 FLOP_PER_PAIR = 30           # per evaluated pair; FMA = 2, rsqrt = 1
 R_MAX, EPS = 3.0, 0.1
+REL_RMS_TOL = 1e-5           # relative RMS against the FP64 oracle
 
 WORKLOADS = {
     "zeldovich128": "128^3 Zel'dovich-displaced lattice (P(k) ~ k^-2 to Nyquist, rms 0.5), "
@@ -58,8 +64,42 @@ def measured_traffic(workload: str):
     return d["traffic_bytes"] if h.hexdigest() == d["source_sha256"] else None
 
 
-def cpu_baseline(p, poly, seconds: float):
-    """Times the oracle on a seeded target sample sized for ~`seconds`."""
+def accuracy_figures(a_gpu, ref) -> dict:
+    """relRMS, max relative error and per-particle bound failures of float32
+    accelerations against the oracle (bound |da| <= 1e-3 |a| + 1e-6 S + A)."""
+    import numpy as np
+    ar = ref["a"]
+    err = np.linalg.norm(a_gpu - ar, axis=1)
+    nref = np.linalg.norm(ar, axis=1)
+    den = float((nref ** 2).sum())
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(nref > 0, err / nref, 0.0)
+    bound = 1e-3 * nref + 1e-6 * ref["S"] + ref["A"]
+    zero = ref["passive"] | ((ref["npair"] == 0) & (ref["A"] == 0))
+    # targets with a pair inside the cutoff tie band, which float32 may
+    # classify either way (the per-particle bound's A term)
+    tie = ref["A"] > 0
+    den_nt = float((nref[~tie] ** 2).sum())
+    return {"reference": "FP64 brute-force oracle (minimum image, same targets)",
+            "targets": int(ar.shape[0]),
+            "rel_rms": float(np.sqrt((err ** 2).sum() / den)) if den > 0 else 0.0,
+            "max_rel": float(rel.max()) if rel.size else 0.0,
+            "n_bound_fail": int((err > bound).sum()),
+            "n_zero_expected": int(zero.sum()),
+            "n_zero_violations": int((np.abs(a_gpu[zero]) > 0).any(axis=1).sum()),
+            "n_tie_targets": int(tie.sum()),
+            "rel_rms_without_tie_targets": float(np.sqrt((err[~tie] ** 2).sum() / den_nt))
+            if den_nt > 0 else 0.0,
+            "tolerance": {"rel_rms": REL_RMS_TOL,
+                          "per_particle": "|da| <= 1e-3 |a| + 1e-6 S + A"},
+            "pass": bool(den == 0 or np.sqrt((err ** 2).sum() / den) <= REL_RMS_TOL)
+            and int((err > bound).sum()) == 0}
+
+
+def cpu_baseline(p, poly, seconds: float, accel=None):
+    """Times the oracle on a seeded target sample sized for ~`seconds`.  With
+    accel (an (n, 3) host array of the GPU result), also returns the accuracy
+    of that result on the sampled targets."""
     import numpy as np
 
     from oracle import oracle as O
@@ -69,6 +109,7 @@ def cpu_baseline(p, poly, seconds: float):
     t_used = 0.0
     total_pairs = 0
     total_targets = 0
+    refs = []
     while True:
         tg = np.sort(rng.choice(p.n, k, replace=False))
         t0 = time.perf_counter()
@@ -78,12 +119,15 @@ def cpu_baseline(p, poly, seconds: float):
         t_used += dt
         total_pairs += int(r["npair"].sum())
         total_targets += k
+        refs.append((tg, r))
         log("cpu_baseline: %d targets in %.2fs" % (k, dt))
-        if t_used >= seconds or k >= p.n:
+        left = seconds - t_used
+        if left < 0.1 * seconds or total_targets >= p.n:
             break
-        k = int(min(p.n, max(k * 2, k * (seconds - t_used) / max(dt, 1e-3))))
-        k = max(64, min(k, p.n))
-    return {
+        # the next sample fills the time left (targets cost about the same)
+        k = int(k * left / max(dt, 1e-3))
+        k = max(64, min(k, p.n - total_targets))
+    base = {
         "value": total_pairs / t_used,
         "unit": "useful pair interactions/s",
         "cores": threads,
@@ -92,58 +136,26 @@ def cpu_baseline(p, poly, seconds: float):
                   "%.1f s; %.3g pair evaluations/s" % (total_targets, p.n, t_used,
                                                        total_targets * p.n / t_used),
     }
+    acc = None
+    if accel is not None:
+        tg = np.concatenate([t for t, _ in refs])
+        ref = {key: np.concatenate([r[key] for _, r in refs]) for key in refs[0][1]}
+        acc = accuracy_figures(accel[tg], ref)
+    return base, acc
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="zeldovich128",
-                    choices=sorted(WORKLOADS) + ["batch64", "serving", "ksk128", "ksk_ml128",
-                                                 "tree"])
-    ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
-    ap.add_argument("--replays", type=int, default=200, help="batch64: timed graph replays")
-    ap.add_argument("--cell", type=float, default=3.0)
-    ap.add_argument("--xsplit", type=int, default=0, help="pair-loop x sub-cells (0: library default)")
-    ap.add_argument("--order", type=int, default=-1, help="work-item order (-1: library default)")
-    ap.add_argument("--persistent", type=int, default=-1, help="persistent pair loop (-1: default)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="first run one 256 MiB device-to-device copy (a known-size kernel "
-                         "for scaling HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
+def bench_single(args, name: str, steps: int, warmup: int, cpu_seconds: float) -> dict:
+    """One resident box, sr_force steps timed with HIP events; returns the
+    fields of the JSON line (value, ms_per_step, config, roofline,
+    cpu_baseline, accuracy)."""
     import numpy as np
     import torch
 
     from paper_1410_2805_amd import gridfit, sr, workloads
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.workload == "batch64":
-        return bench_batch(args)
-    if args.workload == "serving":
-        return bench_serving(args)
-    if args.workload == "ksk128":
-        return bench_step(args)
-    if args.workload == "ksk_ml128":
-        return bench_step_ml(args)
-    if args.workload == "tree":
-        return bench_tree(args)
     dev = torch.device("cuda:0")
-    if args.calib_copy:
-        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    log("generating %s" % args.workload)
-    p = workloads.config(args.workload)
+    log("generating %s" % name)
+    p = workloads.config(name)
     poly = gridfit.poly_coeffs()
     t = {k: torch.from_numpy(getattr(p, k)).to(dev) for k in "xyzm"}
     box = sr.Box.make(p.L, periodic=p.periodic, skin=p.skin)
@@ -161,13 +173,14 @@ def main():
 
     useful, cand, _ = sr.sr_pair_stats(ctx, t["x"], t["y"], t["z"], box, args.cell, R_MAX)
     ncell = sr.sr_grid_dims(box, args.cell)[1]
-    log("pairs: useful %d candidates %d (waste %.2fx)" % (useful, cand, cand / max(useful, 1)))
+    log("%s pairs: useful %d candidates %d (waste %.2fx)" % (name, useful, cand,
+                                                           cand / max(useful, 1)))
 
     def step():
         sr.sr_force(ctx, t["x"], t["y"], t["z"], t["m"], box, args.cell, R_MAX, EPS, poly,
                     out=out, momentum=mom)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     ctx.sync()
     ctx.timing_enable(True)
@@ -176,20 +189,22 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     ev1.record()
     torch.cuda.synchronize()
     ctx.sync()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ms_step = ev0.elapsed_time(ev1) / steps
     prep_ms, force_ms, calls = ctx.timing_collect()
     ctx.timing_enable(False)
     force_avg = force_ms / max(calls, 1)
     prep_avg = prep_ms / max(calls, 1)
-    log("step %.4f ms (prep %.4f ms, pair loop %.4f ms over %d calls)" % (ms_step, prep_avg,
-                                                                        force_avg, calls))
+    log("%s step %.4f ms (prep %.4f ms, pair loop %.4f ms over %d calls)"
+        % (name, ms_step, prep_avg, force_avg, calls))
     achieved = FLOP_PER_PAIR * cand / (force_avg * 1e-3) / 1e12
     value = useful / (ms_step * 1e-3)
+    accel = torch.stack(out, 1).double().cpu().numpy()
+    mom_h = mom.cpu().numpy()
 
     # the same one-box pass replayed as a captured HIP graph (a plan of one box)
     plan = sr.Plan(ctx, [dict(x=t["x"], y=t["y"], z=t["z"], m=t["m"], ax=out[0], ay=out[1],
@@ -198,38 +213,33 @@ def main():
     plan.set_tuning(xsplit=tuning["xsplit"], order=tuning["order"],
                     persistent=tuning["persistent"])
     plan.capture()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.launch()
     torch.cuda.synchronize()
     ev0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.launch()
     ev1.record()
     torch.cuda.synchronize()
-    ms_graph = ev0.elapsed_time(ev1) / args.steps
+    ms_graph = ev0.elapsed_time(ev1) / steps
     plan.close()
-    log("graph replay of the same pass: %.4f ms" % ms_graph)
+    log("%s graph replay of the same pass: %.4f ms" % (name, ms_graph))
+    ctx.close()
+    del t, out
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(p, poly, args.cpu_seconds)
-
-    res = {
-        "metric": "short-range pair interactions/s",
+    cpu = acc = None
+    if cpu_seconds > 0:
+        cpu, acc = cpu_baseline(p, poly, cpu_seconds, accel=accel)
+        log("%s accuracy vs FP64 oracle: relRMS %.3e, max rel %.3e, bound failures %d"
+            % (name, acc["rel_rms"], acc["max_rel"], acc["n_bound_fail"]))
+    bin_min = 16 * p.n + 4 * (ncell + 1)
+    bin_sorted = 48 * p.n + 4 * (ncell + 1)
+    return {
         "value": value,
-        "unit": "useful directed pair interactions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.workload],
-            "name": args.workload,
+            "workload": WORKLOADS[name],
+            "name": name,
             "n": p.n,
             "cell": args.cell,
             "tuning": tuning,
@@ -240,16 +250,16 @@ def main():
             # binning + work items against the algorithmic bytes of binning:
             # 16 B per particle (positions in, permutation out) plus the
             # offsets, or 48 B per particle with the sorted float4 copy
-            "binning_bytes_min": 16 * p.n + 4 * (ncell + 1),
-            "binning_bytes_sorted": 48 * p.n + 4 * (ncell + 1),
-            "binning_effective_GBps_min": (16 * p.n + 4 * (ncell + 1)) / (prep_avg * 1e-3) / 1e9,
-            "binning_effective_GBps_sorted": (48 * p.n + 4 * (ncell + 1)) / (prep_avg * 1e-3)
-            / 1e9,
+            "binning_bytes_min": bin_min,
+            "binning_bytes_sorted": bin_sorted,
+            "binning_effective_GBps_min": bin_min / (prep_avg * 1e-3) / 1e9,
+            "binning_effective_GBps_sorted": bin_sorted / (prep_avg * 1e-3) / 1e9,
             "pair_loop_ms": force_avg,
             "pair_loop_useful_per_s": useful / (force_avg * 1e-3),
             "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
             "graph_replay_ms_per_step": ms_graph,
             "graph_replay_useful_per_s": useful / (ms_graph * 1e-3),
+            "momentum_fp64": [float(v) for v in mom_h],
         },
         "roofline": {
             "bound": "alu",
@@ -258,18 +268,138 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": measured_traffic(args.workload),
+            "traffic": measured_traffic(name),
         },
         "cpu_baseline": cpu,
+        "accuracy": acc,
     }
+
+
+def _nested(fn, label):
+    """Runs one nested measurement; a failure is recorded, not hidden."""
+    try:
+        return fn()
+    except Exception as e:  # reported in the JSON line
+        log("%s failed: %r" % (label, e))
+        return {"error": repr(e)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="nfw256",
+                    choices=sorted(WORKLOADS) + ["batch64", "serving", "ksk128", "ksk_ml128",
+                                                 "tree"])
+    ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
+    ap.add_argument("--replays", type=int, default=200, help="batch64: timed graph replays")
+    ap.add_argument("--cell", type=float, default=3.0)
+    ap.add_argument("--xsplit", type=int, default=0, help="pair-loop x sub-cells (0: library default)")
+    ap.add_argument("--order", type=int, default=-1, help="work-item order (-1: library default)")
+    ap.add_argument("--persistent", type=int, default=-1, help="persistent pair loop (-1: default)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload only: skip the nested zeldovich128, batched and "
+                         "serving measurements")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a read-only pass over a cold 1 GiB buffer and a 256 MiB "
+                         "device-to-device copy (known-size kernels for scaling HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batch64":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
+    if args.workload == "ksk128":
+        return bench_step(args)
+    if args.workload == "ksk_ml128":
+        return bench_step_ml(args)
+    if args.workload == "tree":
+        return bench_tree(args)
+    if args.calib_copy:
+        calibration_kernels()
+    cpu_s = 0.0 if args.no_cpu_baseline else args.cpu_seconds
+    r = bench_single(args, args.workload, args.steps, args.warmup, cpu_s)
+    res = {
+        "metric": "short-range pair interactions/s + % FP32 peak; p50/p99 latency (batched)",
+        "value": r["value"],
+        "unit": "useful directed pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": r["config"],
+        "roofline": r["roofline"],
+        "cpu_baseline": r["cpu_baseline"],
+        "accuracy": r["accuracy"],
+    }
+    if args.workload == "nfw256" and not args.headline_only:
+        def zel():
+            z = bench_single(args, "zeldovich128", 50, 5, 0.5 * cpu_s)
+            z["config"]["useful_pairs_per_s"] = z["value"]
+            z["config"]["ms_per_step"] = z["ms_per_step"]
+            return {"config": z["config"], "roofline": z["roofline"],
+                    "cpu_baseline": z["cpu_baseline"], "accuracy": z["accuracy"]}
+
+        def batched():
+            b = bench_batch(args)
+            return {"workload": b["config"]["workload"], "tuning": b["config"]["tuning"],
+                    "latency_ms": b["latency_ms"], "useful_pairs_per_s": b["value"],
+                    "loop_of_single_box_calls_ms": b["loop_of_single_box_calls_ms"],
+                    "speedup_vs_loop": b["speedup_vs_loop"]}
+
+        def serving():
+            s = bench_serving(args, cpu=cpu_s > 0)
+            return {"workload": s["config"]["workload"], "server": s["server"],
+                    "fifo_baseline": s["fifo_baseline"],
+                    "throughput_ratio_vs_fifo": s["throughput_ratio_vs_fifo"],
+                    "saturation": s["saturation"], "accuracy": s["accuracy"]}
+
+        res["config"]["zeldovich128"] = _nested(zel, "zeldovich128")
+        res["config"]["batched"] = _nested(batched, "batched")
+        res["config"]["serving"] = _nested(serving, "serving")
     print(json.dumps(res), flush=True)
-    ctx.close()
 
 
-def bench_batch(args):
+def calibration_kernels():
+    """Known-size kernels for scaling HBM counters: a read-only sum over a
+    1 GiB buffer written long before (cold: 4x the 256 MB Infinity Cache),
+    and a 256 MiB device-to-device copy."""
+    import torch
+    dev = torch.device("cuda:0")
+    cold = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    s = cold.sum()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration: sum %.0f" % float(s))
+    del a, b, cold
+
+
+def bench_batch(args) -> dict:
     """64 independent periodic boxes (16^3..96^3 particles, half uniform,
-    half clustered) in one plan: autotuned, captured in a HIP graph, timed
-    per replay; compared with a loop of plain single-box sr_force calls."""
+    half clustered) in one plan, in split (cell + float32 offset)
+    coordinates from FP64 master positions: autotuned, captured in a HIP
+    graph, timed per replay; compared with a loop of plain single-box
+    sr_force_split calls at the same tuning."""
     import numpy as np
     import torch
 
@@ -279,19 +409,22 @@ def bench_batch(args):
     poly = gridfit.poly_coeffs()
     specs = workloads.batch_specs(64, seed=4)
     log("generating 64 boxes (%d particles)" % sum(s.n for s in specs))
+    ctx = sr.Context(0)
     boxes = []
+    useful = 0
     for sp in specs:
         p = workloads.make_box(sp)
-        t = {k: torch.from_numpy(getattr(p, k)).to(dev) for k in "xyzm"}
-        t.update({k: torch.empty(p.n, dtype=torch.float32, device=dev) for k in ("ax", "ay", "az")})
-        t["box"] = sr.Box.make(p.L)
-        t["cell"] = 3.0
-        boxes.append(t)
-    ctx = sr.Context(0)
-    useful = 0
-    for t in boxes:
-        u, _, _ = sr.sr_pair_stats(ctx, t["x"], t["y"], t["z"], t["box"], 3.0, R_MAX)
+        box = sr.Box.make(p.L)
+        g = {k: torch.from_numpy(getattr(p, k)).to(dev) for k in "xyz"}
+        u, _, _ = sr.sr_pair_stats(ctx, g["x"], g["y"], g["z"], box, 3.0, R_MAX)
         useful += u
+        x64 = [torch.from_numpy(np.ascontiguousarray(c)).to(dev) for c in p.pos64().T]
+        c3, ox, oy, oz = sr.sr_split_from_f64(ctx, x64[0], x64[1], x64[2], box, 3.0)
+        t = {"x": ox, "y": oy, "z": oz, "cell3": c3, "m": torch.from_numpy(p.m).to(dev),
+             "box": box, "cell": 3.0}
+        t.update({k: torch.empty(p.n, dtype=torch.float32, device=dev) for k in ("ax", "ay", "az")})
+        boxes.append(t)
+        del g, x64
     mom = torch.zeros(3 * len(boxes), dtype=torch.float64, device=dev)
     plan = sr.Plan(ctx, boxes, R_MAX, EPS, poly, momentum=mom)
     best, best_ms = plan.autotune(reps=3)
@@ -310,12 +443,11 @@ def bench_batch(args):
     lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
     # baseline: the same boxes by a loop of single-box calls, same tuning
     ctx.set_tuning(xsplit=best["xsplit"], order=best["order"], persistent=best["persistent"])
-    cell = 3.0 * best["cell_scale"]
 
     def loop():
         for t in boxes:
-            sr.sr_force(ctx, t["x"], t["y"], t["z"], t["m"], t["box"], cell, R_MAX, EPS, poly,
-                        out=(t["ax"], t["ay"], t["az"]))
+            sr.sr_force_split(ctx, t["cell3"], t["x"], t["y"], t["z"], t["m"], t["box"], 3.0,
+                              R_MAX, EPS, poly, out=(t["ax"], t["ay"], t["az"]))
 
     for _ in range(3):
         loop()
@@ -329,6 +461,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     loop_ms = e0.elapsed_time(e1) / reps
     p50 = float(np.percentile(lat, 50))
+    log("batched: p50 %.3f ms, p99 %.3f ms; loop of single-box calls %.3f ms"
+        % (p50, float(np.percentile(lat, 99)), loop_ms))
     res = {
         "metric": "batched short-range pass latency (64 boxes, one graph launch)",
         "value": useful / (p50 * 1e-3),
@@ -337,17 +471,20 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "64 periodic boxes, N log-uniform in [16^3, 96^3] (total %d), "
-                               "half uniform, half NFW-clustered, r_max=3, eps=0.1, cell 3"
-                               % sum(s.n for s in specs),
+                               "half uniform, half NFW-clustered, split (cell + float32 offset) "
+                               "coordinates from FP64 masters, r_max=3, eps=0.1, cell 3, FP64 "
+                               "momentum per box" % sum(s.n for s in specs),
                    "tuning": best, "useful_pairs": useful},
         "latency_ms": {"p50": p50, "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "replays": int(lat.size)},
         "loop_of_single_box_calls_ms": loop_ms,
         "speedup_vs_loop": loop_ms / p50,
+        "roofline": None,
+        "cpu_baseline": None,
     }
-    print(json.dumps(res), flush=True)
     plan.close()
     ctx.close()
+    return res
 
 
 def bench_step(args):
@@ -663,11 +800,48 @@ def bench_tree(args):
     print(json.dumps(res), flush=True)
 
 
-def bench_serving(args):
+def serving_accuracy(trace, boxes, srv_res, fifo_res, poly, rids) -> dict:
+    """Both paths' final states of sampled requests against full FP64
+    stream-kick-stream trajectories of the oracle (boxes of at most 28^3
+    particles, where the O(N^2) oracle takes seconds)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    out = []
+    for rq in trace:
+        if rq.rid not in rids:
+            continue
+        pos, vel, mass = boxes.get(rq.ngrid)
+        L = float(rq.ngrid)
+        P, V = pos.copy(), vel.astype(np.float64)
+        for _ in range(rq.steps):
+            P, V, _ = O.sks(P, V, mass, L, R_MAX, EPS, poly.astype(np.float64), 0.05)
+        item = {"rid": rq.rid, "n": int(mass.shape[0]), "steps": rq.steps}
+        finals = {}
+        for name, res in (("server", srv_res), ("fifo", fifo_res)):
+            op, ov = res[rq.rid]
+            x = np.stack([np.asarray(a, np.float64) for a in op], 1)
+            v = np.stack([np.asarray(a, np.float64) for a in ov], 1)
+            d = x - P
+            d -= L * np.round(d / L)
+            item[name] = {"max_abs_pos_err": float(np.abs(d).max()),
+                          "rms_pos_err": float(np.sqrt((d ** 2).sum(1).mean())),
+                          "max_abs_vel_err": float(np.abs(v - V).max())}
+            finals[name] = (x, v)
+        item["bitwise_equal"] = bool(np.array_equal(finals["server"][0], finals["fifo"][0]) and
+                                     np.array_equal(finals["server"][1], finals["fifo"][1]))
+        out.append(item)
+    return {"reference": "FP64 oracle, full stream-kick-stream trajectories (dt 0.05)",
+            "requests": out}
+
+
+def bench_serving(args, cpu: bool = True) -> dict:
     """Poisson-arriving requests (mean 200/s), Zel'dovich boxes of 24^3..128^3
     particles, 10 SKS steps each, served by continuous batching; then the same
-    trace by a FIFO loop of plain single-box calls."""
-    import torch
+    trace by a FIFO loop of plain single-box calls on the same split
+    coordinates (sr_sks_split: equal accuracy); then both paths saturated
+    (all arrivals at t = 0) on the first 400 requests."""
+    import torch  # noqa: F401
 
     from paper_1410_2805_amd import gridfit, serving, sr, workloads
 
@@ -678,22 +852,41 @@ def bench_serving(args):
     log("generating %d distinct boxes" % len(sizes))
     t0 = time.perf_counter()
     for k, ng in enumerate(sizes):
-        boxes.get(ng)
+        boxes.soa(ng)  # page-locked inputs, made before the trace starts
         if time.perf_counter() - t0 > 5:
             log("  %d/%d" % (k + 1, len(sizes)))
             t0 = time.perf_counter()
+    # requests whose trajectories the oracle checks (small boxes, spread over the trace)
+    small = [r.rid for r in trace if r.ngrid <= 28]
+    rids = set(small[:: max(1, len(small) // 3)][:3]) if cpu else set()
+    xs = args.xsplit if args.xsplit else 2
     ctx = sr.Context(0)
-    srv = sr.Server(ctx, 64 << 30, 64, R_MAX, EPS, poly, 3.0,
-                    **({"xsplit": args.xsplit} if args.xsplit else {}))
+    srv = sr.Server(ctx, 64 << 30, 64, R_MAX, EPS, poly, 3.0, xsplit=xs)
     # warm-up request (compilation, allocator)
     warm = workloads.serving_trace(4, rate=1000.0, seed=99, ng_lo=24, ng_hi=32)
     serving.run_server(srv, warm, boxes)
     log("serving %d requests" % len(trace))
-    r_srv = serving.run_server(srv, trace, boxes, log=log)
+    r_srv = serving.run_server(srv, trace, boxes, keep_results=rids, log=log)
     info = srv.info()
+    log("server: p50 %.1f ms, p99 %.1f ms, %.3g particle-steps/s"
+        % (1e3 * r_srv["latency_p50_s"], 1e3 * r_srv["latency_p99_s"],
+           r_srv["particle_steps_per_s"]))
+    sat = trace[:400]
+    s_srv = serving.run_server(srv, sat, boxes, time_scale=0.0)
     srv.close()
+    ctx.set_tuning(xsplit=xs)
     log("fifo baseline")
-    r_fifo = serving.run_fifo(ctx, trace, boxes, R_MAX, EPS, poly, 3.0, log=log)
+    r_fifo = serving.run_fifo(ctx, trace, boxes, R_MAX, EPS, poly, 3.0, keep_results=rids,
+                              log=log)
+    log("fifo: p50 %.1f ms, p99 %.1f ms, %.3g particle-steps/s"
+        % (1e3 * r_fifo["latency_p50_s"], 1e3 * r_fifo["latency_p99_s"],
+           r_fifo["particle_steps_per_s"]))
+    s_fifo = serving.run_fifo(ctx, sat, boxes, R_MAX, EPS, poly, 3.0, time_scale=0.0)
+    ctx.close()
+    acc = None
+    if rids:
+        acc = serving_accuracy(trace, boxes, r_srv["results"], r_fifo["results"], poly, rids)
+    strip = ("results",)
     res = {
         "metric": "serving latency p50/p99 and throughput (continuous batching)",
         "value": r_srv["particle_steps_per_s"],
@@ -704,15 +897,24 @@ def bench_serving(args):
         "data": "synthetic",
         "config": {"workload": "%d Poisson requests at 200/s, Zel'dovich boxes N = ngrid^3, "
                                "ngrid log-uniform in [24, 128], 10 SKS steps (dt 0.05), split "
-                               "coordinates, HBM budget 64 GiB, 64 slots" % len(trace),
+                               "coordinates, HBM budget 64 GiB, 64 slots, x sub-cells %d"
+                               % (len(trace), xs),
                    "state_bytes_high_water": info["state_bytes_high_water"],
                    "ticks": r_srv["ticks"]},
-        "server": {k: v for k, v in r_srv.items() if k != "results"},
-        "fifo_baseline": r_fifo,
+        "server": {k: v for k, v in r_srv.items() if k not in strip},
+        "fifo_baseline": {k: v for k, v in r_fifo.items() if k not in strip},
         "throughput_ratio_vs_fifo": r_srv["particle_steps_per_s"] / r_fifo["particle_steps_per_s"],
+        "saturation": {"requests": len(sat), "arrivals": "all at t = 0",
+                       "server_particle_steps_per_s": s_srv["particle_steps_per_s"],
+                       "fifo_particle_steps_per_s": s_fifo["particle_steps_per_s"],
+                       "ratio": s_srv["particle_steps_per_s"] / s_fifo["particle_steps_per_s"],
+                       "server_latency_p50_s": s_srv["latency_p50_s"],
+                       "fifo_latency_p50_s": s_fifo["latency_p50_s"]},
+        "accuracy": acc,
+        "roofline": None,
+        "cpu_baseline": None,
     }
-    print(json.dumps(res), flush=True)
-    ctx.close()
+    return res
 
 
 if __name__ == "__main__":

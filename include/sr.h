@@ -88,7 +88,10 @@ int sr_ctx_destroy(sr_ctx *ctx);
  * string is owned by the context and valid until its next call. */
 const char *sr_last_error(const sr_ctx *ctx);
 
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on.  Every call of a context shares
+ * its scratch arena, so the new stream is made to wait (on the device, no
+ * host wait) for the work already enqueued on the old one before anything
+ * enqueued afterwards can start.  SR_EDEVICE if that ordering fails. */
 int sr_set_stream(sr_ctx *ctx, void *hip_stream);
 
 /* Bytes of arena currently allocated, and the high-water need so far. */
@@ -227,6 +230,20 @@ int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox, const flo
                    float r_max, float eps, const float poly[6], float *ax, float *ay, float *az,
                    double *momentum3);
 
+/* One stream-kick-stream step (Sec. 2.5) of one periodic box held in split
+ * coordinates, with the short-range force only:
+ *   o += v dt/2 (FP64, re-homed);  a = sr_force_split;  v += a dt;
+ *   o += v dt/2 (FP64, re-homed).
+ * These are the maps of the serving form (sr_server_*): a box stepped by this
+ * call follows bitwise the trajectory it follows inside a server with the
+ * same cell and tuning.  cell3, ox, oy, oz, vx, vy, vz (device) are updated in
+ * place; ax, ay, az (device float32[n]) receive the step's accelerations.
+ * Arguments, scratch and errors as sr_force_split; dt finite. */
+int sr_sks_split(sr_ctx *ctx, int32_t *cell3, float *ox, float *oy, float *oz, float *vx,
+                 float *vy, float *vz, const float *mass, int64_t n, const sr_box *box,
+                 double cell, float r_max, float eps, const float poly[6], float dt, float *ax,
+                 float *ay, float *az);
+
 /* ---- FP64 reductions on the device ------------------------------------ */
 
 /* Kinetic energy K = sum_i m_i |v_i|^2 / 2 in FP64 (device float32 inputs,
@@ -264,13 +281,19 @@ int sr_tree_leaves(sr_ctx *ctx, const float *x, const float *y, const float *z, 
 /* ---- Batched form: many independent boxes per pass -------------------- */
 
 /* One box of a batch: device float32 inputs and outputs of its own, its own
- * geometry and chaining cell.  Boxes never interact. */
+ * geometry and chaining cell.  Boxes never interact.
+ *   cell3 == NULL : x, y, z are global coordinates (as sr_force).
+ *   cell3 != NULL : split coordinates of a periodic box (as sr_force_split):
+ *                   cell3 holds the packed chaining cells of the mesh given
+ *                   by `cell` and x, y, z the float32 offsets.  Such a box
+ *                   needs cell_scale 1 and uses min(xsplit, 3) x sub-cells. */
 typedef struct sr_batch_box {
     const float *x, *y, *z, *mass;
     int64_t n;
     sr_box box;
     double cell;
     float *ax, *ay, *az;
+    const int32_t *cell3;
 } sr_batch_box;
 
 typedef struct sr_plan sr_plan;
@@ -288,7 +311,8 @@ typedef struct sr_plan sr_plan;
  *                lands in momentum[3b .. 3b+2].
  * The plan owns its scratch (sized for every tuning) and its descriptor
  * table; creation waits for the upload.  Each box's accelerations are
- * bitwise those of sr_force on that box alone with the same sr_tuning.
+ * bitwise those of sr_force (sr_force_split for a box with cell3) on that
+ * box alone with the same sr_tuning.
  * Errors: SR_EINVAL (a bad box, with its index in sr_last_error),
  * SR_ENOMEM, SR_EDEVICE. */
 int sr_plan_create(sr_ctx *ctx, const sr_batch_box *boxes, int nboxes, float r_max, float eps,

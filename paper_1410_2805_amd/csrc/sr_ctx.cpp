@@ -140,7 +140,10 @@ extern "C" int sr_ctx_create(int device, void *hip_stream, size_t arena_bytes, s
     }
     ctx->status = (int *)p;
     ctx->stats = (int64_t *)((char *)p + 64);
-    if (hipMemset(p, 0, 256) != hipSuccess) {
+    if (hipMemset(p, 0, 256) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->handoff, hipEventDisableTiming) != hipSuccess) {
+        if (ctx->handoff)
+            (void)hipEventDestroy(ctx->handoff);
         (void)hipFree(p);
         delete ctx;
         return SR_EDEVICE;
@@ -150,6 +153,7 @@ extern "C" int sr_ctx_create(int device, void *hip_stream, size_t arena_bytes, s
         if (hipMalloc(&p, arena_bytes) != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(ctx->status);
+            (void)hipEventDestroy(ctx->handoff);
             delete ctx;
             return SR_ENOMEM;
         }
@@ -172,6 +176,8 @@ extern "C" int sr_ctx_destroy(sr_ctx *ctx)
         (void)hipFree(ctx->status);
     for (hipEvent_t e : ctx->events)
         (void)hipEventDestroy(e);
+    if (ctx->handoff)
+        (void)hipEventDestroy(ctx->handoff);
     delete ctx;
     return SR_OK;
 }
@@ -262,11 +268,22 @@ extern "C" const char *sr_last_error(const sr_ctx *ctx)
     return ctx ? ctx->err.c_str() : "context is NULL";
 }
 
+// Every call shares the context's scratch arena, status word and counters,
+// so work enqueued on a new stream must not start before the work already
+// queued on the old one: the new stream waits for an event recorded on the
+// old one (no host wait).
 extern "C" int sr_set_stream(sr_ctx *ctx, void *hip_stream)
 {
     if (!ctx)
         return SR_EINVAL;
-    ctx->stream = (hipStream_t)hip_stream;
+    const hipStream_t next = (hipStream_t)hip_stream;
+    if (next == ctx->stream)
+        return SR_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipEventRecord(ctx->handoff, ctx->stream) != hipSuccess ||
+        hipStreamWaitEvent(next, ctx->handoff, 0) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "ordering the new stream after the old one failed");
+    ctx->stream = next;
     return SR_OK;
 }
 

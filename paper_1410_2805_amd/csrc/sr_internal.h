@@ -17,6 +17,7 @@ struct sr_ctx {
     size_t arena_cap = 0;
     size_t high_water = 0;
     bool fixed = false;         // fixed-size arena: never regrow
+    hipEvent_t handoff = nullptr;  // orders a new stream after the old one (sr_set_stream)
     int *status = nullptr;      // device status word (bit 0: bad coordinate)
     int64_t *stats = nullptr;   // device counters for sr_pair_stats
     std::string err;

@@ -53,6 +53,13 @@ void drop_graph(sr_plan *p)
     p->graph = nullptr;
 }
 
+// x sub-cells of box bx under tuning t: split-coordinate boxes take at most
+// 3 (their stencil has one piece per cell, 9 (2 xsplit + 1) <= 63).
+int box_xsplit(const sr_batch_box &bx, const sr_tuning &t)
+{
+    return bx.cell3 && t.xsplit > 3 ? 3 : t.xsplit;
+}
+
 // Geometry of every box under a tuning; returns SR_EINVAL naming the box.
 int box_geoms(sr_plan *p, const sr_tuning &t, std::vector<Geom> &g, int64_t *ctot)
 {
@@ -60,10 +67,26 @@ int box_geoms(sr_plan *p, const sr_tuning &t, std::vector<Geom> &g, int64_t *cto
     int64_t c = 0;
     for (size_t b = 0; b < p->boxes.size(); ++b) {
         const sr_batch_box &bx = p->boxes[b];
-        int rc = check_box_args(p->ctx, &bx.box, bx.cell * (double)t.cell_scale, p->r_max,
-                                t.xsplit, &g[b]);
+        const int xs = box_xsplit(bx, t);
+        int rc = check_box_args(p->ctx, &bx.box, bx.cell * (double)t.cell_scale, p->r_max, xs,
+                                &g[b]);
         if (rc)
             return sr_fail(p->ctx, rc, "box %zu: %s", b, p->ctx->err.c_str());
+        if (bx.cell3) {
+            // the offsets are relative to the mesh of `cell`: no other mesh
+            if (t.cell_scale != 1.0f)
+                return sr_fail(p->ctx, SR_EINVAL, "box %zu: split coordinates need cell_scale 1",
+                               b);
+            if (!bx.box.periodic)
+                return sr_fail(p->ctx, SR_EINVAL, "box %zu: split coordinates need a periodic box",
+                               b);
+            for (int d = 0; d < 3; ++d)
+                if (g[b].nc[d] / (d == 0 ? xs : 1) > kSplitMaxCells)
+                    return sr_fail(p->ctx, SR_EINVAL,
+                                   "box %zu: split coordinates allow at most %d cells per axis", b,
+                                   kSplitMaxCells);
+            g[b].split = 1;
+        }
         c += g[b].ncell;
         if (c > 2147483646LL)
             return sr_fail(p->ctx, SR_EINVAL, "too many cells in the batch");
@@ -99,6 +122,7 @@ int configure(sr_plan *p, const sr_tuning &t)
         d[b].y = bx.y;
         d[b].z = bx.z;
         d[b].m = bx.mass;
+        d[b].cell3 = bx.cell3;
         d[b].ax = bx.ax;
         d[b].ay = bx.ay;
         d[b].az = bx.az;

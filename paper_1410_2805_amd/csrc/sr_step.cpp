@@ -137,3 +137,40 @@ extern "C" int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, fl
     return kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, lr_ax, lr_ay, lr_az,
                                half_dt, 0.0);
 }
+
+extern "C" int sr_sks_split(sr_ctx *ctx, int32_t *cell3, float *ox, float *oy, float *oz,
+                            float *vx, float *vy, float *vz, const float *mass, int64_t n,
+                            const sr_box *box, double cell, float r_max, float eps,
+                            const float poly[6], float dt, float *ax, float *ay, float *az)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > INT_MAX)
+        return sr_fail(ctx, SR_EINVAL, "n out of range");
+    if (n > 0 && (!vx || !vy || !vz))
+        return sr_fail(ctx, SR_EINVAL, "NULL velocity pointer with n > 0");
+    if (!std::isfinite(dt))
+        return sr_fail(ctx, SR_EINVAL, "dt must be finite");
+    SplitGeom sg;
+    int rc = split_geom(ctx, box, cell, &sg);
+    if (rc)
+        return rc;
+    // validates the remaining arguments before anything is enqueued
+    size_t bytes = 0;
+    if ((rc = force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box, cell, r_max, eps, poly, ax,
+                                 ay, az, nullptr, nullptr, &bytes)))
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    const int ni = (int)n;
+    // the serving maps: stream by dt/2 in FP64, kick by fl32(dt)
+    const double half = 0.5 * (double)dt;
+    if ((rc = kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, nullptr, nullptr,
+                                  nullptr, 0.f, half)))
+        return rc;
+    if ((rc = force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box, cell, r_max, eps, poly, ax,
+                                 ay, az, nullptr, nullptr, nullptr)))
+        return rc;
+    return kick_stream_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, ax, ay, az, dt, half);
+}

@@ -58,7 +58,7 @@ class BatchBox(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("mass", ctypes.c_void_p), ("n", ctypes.c_int64), ("box", Box),
                 ("cell", ctypes.c_double), ("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p),
-                ("az", ctypes.c_void_p)]
+                ("az", ctypes.c_void_p), ("cell3", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -133,6 +133,8 @@ def _load():
         "sr_split_to_f64": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, P, P, P]),
         "sr_force_split": (ctypes.c_int, [P, P, P, P, P, P, i64, BP, f64, f32, f32, P, P, P, P,
                                           P]),
+        "sr_sks_split": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, i64, BP, f64, f32, f32, P,
+                                        f32, P, P, P]),
         "sr_plan_create": (ctypes.c_int, [P, ctypes.POINTER(BatchBox), ctypes.c_int, f32, f32, P,
                                           P, ctypes.POINTER(P)]),
         "sr_plan_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
@@ -183,7 +185,7 @@ def exported_symbols() -> list[str]:
     return ["sr_ctx_create", "sr_ctx_destroy", "sr_last_error", "sr_set_stream", "sr_arena_info",
             "sr_sync", "sr_grid_dims", "sr_scratch_bytes", "sr_bin", "sr_force", "sr_pair_stats",
             "sr_timing_enable", "sr_timing_collect", "sr_set_tuning", "sr_get_tuning",
-            "sr_split_from_f64", "sr_split_to_f64", "sr_force_split",
+            "sr_split_from_f64", "sr_split_to_f64", "sr_force_split", "sr_sks_split",
             "sr_plan_create", "sr_plan_set_tuning", "sr_plan_get_tuning", "sr_plan_run",
             "sr_plan_capture", "sr_plan_launch", "sr_plan_autotune", "sr_plan_destroy",
             "sr_server_create", "sr_server_submit", "sr_server_tick", "sr_server_poll",
@@ -386,6 +388,25 @@ def sr_force_split(ctx: Context, cell3, ox, oy, oz, m, box: Box, cell: float, r_
     return ax, ay, az, mom
 
 
+def sr_sks_split(ctx: Context, state: dict, box: Box, cell: float, r_max: float, eps: float,
+                 poly, dt: float, out=None):
+    """One stream-kick-stream step of one box of split state (the serving
+    maps), in place on state's cell3, ox, oy, oz, vx, vy, vz (mass m);
+    returns the step's accelerations (ax, ay, az)."""
+    n = int(state["cell3"].shape[0])
+    dev = state["cell3"].device
+    if out is None:
+        out = tuple(torch.empty(max(n, 1), dtype=torch.float32, device=dev)[:n] for _ in range(3))
+    c = (ctypes.c_float * 6)(*[float(v) for v in poly])
+    ctx._bind_stream()
+    ctx._check(lib.sr_sks_split(ctx._h, _typed(state["cell3"], n, torch.int32, "cell3"),
+                                *(_f32(state[k], n, k) for k in ("ox", "oy", "oz", "vx", "vy",
+                                                                  "vz", "m")),
+                                n, ctypes.byref(box), float(cell), float(r_max), float(eps), c,
+                                float(dt), *(_f32(a, n, "a") for a in out)))
+    return out
+
+
 def sr_force_tree(ctx: Context, x, y, z, m, box: Box, cell: float, r_max: float, eps: float,
                   poly, leaf_max: int = 128, out=None, momentum: bool = False):
     """sr_force through RCB trees in the chaining cells (include/sr.h)."""
@@ -449,7 +470,9 @@ class Plan:
     """sr_plan: a batch of independent boxes evaluated in one pass.
 
     boxes: list of dicts with device tensors x, y, z, m, outputs ax, ay, az,
-    and box (Box), cell (float).  The tensors must outlive the plan."""
+    and box (Box), cell (float); a box with an int32 tensor "cell3" is in
+    split coordinates (x, y, z are then the offsets).  The tensors must
+    outlive the plan."""
 
     def __init__(self, ctx: Context, boxes, r_max: float, eps: float, poly, momentum=None):
         self.ctx = ctx
@@ -466,6 +489,9 @@ class Plan:
             arr[i].box = b["box"]
             arr[i].cell = float(b["cell"])
             arr[i].ax, arr[i].ay, arr[i].az = (b[k].data_ptr() for k in ("ax", "ay", "az"))
+            if b.get("cell3") is not None:
+                arr[i].cell3 = _typed(b["cell3"], n, torch.int32, "cell3")
+                self._keep.append(b["cell3"])
         if momentum is not None:
             if not (momentum.is_cuda and momentum.dtype == torch.float64
                     and momentum.numel() == 3 * len(boxes) and momentum.is_contiguous()):
@@ -520,8 +546,11 @@ class Plan:
 class Server:
     """sr_server: continuous batching of stream-kick-stream requests.
 
-    submit() takes numpy host arrays; the caller keeps them alive until the
-    request completes (output arrays should be pinned, see pinned_empty)."""
+    submit() takes numpy host arrays, positions and velocities either as
+    (n, 3) arrays (copied) or as tuples of three contiguous 1-D arrays (used
+    in place); the caller keeps them alive until the request completes.
+    Pinned arrays (pinned_empty) keep the input and result copies
+    asynchronous; pageable ones make each admission wait for its copy."""
 
     def __init__(self, ctx: Context, hbm_budget: int, max_slots: int, r_max: float, eps: float,
                  poly, cell: float, xsplit: int = 2, order: int = 1, persistent: int = 0):
@@ -547,9 +576,16 @@ class Server:
         receives the final state's FP64 kinetic energy."""
         import numpy as np
         n = int(mass.shape[0])
-        arrs = [np.ascontiguousarray(pos64[:, d], dtype=np.float64) for d in range(3)]
-        arrs += [np.ascontiguousarray(vel[:, d], dtype=np.float32) for d in range(3)]
-        arrs += [np.ascontiguousarray(mass, dtype=np.float32)]
+        if isinstance(pos64, (tuple, list)):
+            # structure of arrays, used in place (pinned arrays keep the
+            # admission copies asynchronous)
+            arrs = list(pos64) + list(vel) + [mass]
+            for a, dt_ in zip(arrs, [np.float64] * 3 + [np.float32] * 4):
+                assert a.dtype == dt_ and a.flags["C_CONTIGUOUS"] and a.shape == (n,)
+        else:
+            arrs = [np.ascontiguousarray(pos64[:, d], dtype=np.float64) for d in range(3)]
+            arrs += [np.ascontiguousarray(vel[:, d], dtype=np.float32) for d in range(3)]
+            arrs += [np.ascontiguousarray(mass, dtype=np.float32)]
         for a in list(out_pos) + list(out_vel):
             assert a.flags["C_CONTIGUOUS"] and a.shape[0] == n
         r = Request()

@@ -182,6 +182,43 @@ def test_edge_cases(sr, ctx, poly):
     check_accel(a, _ref(co, poly), "coincident")
 
 
+def test_stream_switch_orders_shared_scratch(sr, poly):
+    """Two calls of one context on two streams share its scratch arena: the
+    second stream must wait for the first call's kernels (results of both
+    equal the same calls made one after the other on one stream)."""
+    ctx = sr.Context(0)
+    try:
+        pa = W.zeldovich(64, 64.0, 7)
+        pb = W.uniform(200000, 60.0, 8)
+        ta, tb = to_dev(pa), to_dev(pb)
+        ba, bb = sr.Box.make(64.0), sr.Box.make(60.0)
+        ref_a = accel_np(*sr.sr_force(ctx, ta["x"], ta["y"], ta["z"], ta["m"], ba, 3.0, R_MAX, EPS,
+                                      poly)[:3])
+        ref_b = accel_np(*sr.sr_force(ctx, tb["x"], tb["y"], tb["z"], tb["m"], bb, 3.0, R_MAX, EPS,
+                                      poly)[:3])
+        ctx.sync()
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        outs = []
+        for rep in range(3):
+            with torch.cuda.stream(s1):
+                oa = tuple(torch.empty(pa.n, device="cuda:0") for _ in range(3))
+                sr.sr_force(ctx, ta["x"], ta["y"], ta["z"], ta["m"], ba, 3.0, R_MAX, EPS, poly,
+                            out=oa)
+            with torch.cuda.stream(s2):
+                ob = tuple(torch.empty(pb.n, device="cuda:0") for _ in range(3))
+                sr.sr_force(ctx, tb["x"], tb["y"], tb["z"], tb["m"], bb, 3.0, R_MAX, EPS, poly,
+                            out=ob)
+            outs.append((oa, ob))
+        torch.cuda.synchronize()
+        ctx.sync()
+        for oa, ob in outs:
+            assert np.array_equal(accel_np(*oa), ref_a)
+            assert np.array_equal(accel_np(*ob), ref_b)
+    finally:
+        ctx.close()
+
+
 def test_invalid_args(sr, ctx, poly):
     p = W.uniform(100, 12.0, 1)
     t = to_dev(p)
