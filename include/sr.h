@@ -153,6 +153,31 @@ int sr_force(sr_ctx *ctx, const float *x, const float *y, const float *z, const 
              int64_t n, const sr_box *box, double cell, float r_max, float eps,
              const float poly[6], float *ax, float *ay, float *az, double *momentum3);
 
+/* sr_force for callers that cannot allocate device memory while they run:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Arguments, outputs, errors and results are those of sr_force
+ * (bitwise, at the same tuning); the difference is where the scratch lives.
+ * Instead of the context arena (which sr_force may grow with hipMalloc) the
+ * call uses one fixed device array of sr_force_static_capacity() bytes
+ * (128 MiB) per GPU, held from the library's load until the process ends;
+ * this call allocates nothing (no hipMalloc, no events, no library
+ * allocation).  About 40 bytes per particle plus 12 per chaining cell are
+ * needed: a 128^3-particle box with 3-unit cells fits; a call needing more
+ * returns SR_ENOMEM with a message and enqueues nothing.  No timing record
+ * is taken (sr_timing_collect does not see these calls).
+ * Concurrency: every call on one GPU shares that GPU's array, whatever its
+ * context or stream, and the array keeps the last call's contents (each
+ * call clears what it needs zeroed).  Calls that may overlap on one GPU --
+ * on different streams, or from different threads -- race on it: serialize
+ * them (one stream, or events between the streams). */
+int sr_force_static(sr_ctx *ctx, const float *x, const float *y, const float *z,
+                    const float *mass, int64_t n, const sr_box *box, double cell, float r_max,
+                    float eps, const float poly[6], float *ax, float *ay, float *az,
+                    double *momentum3);
+
+/* Bytes of sr_force_static's fixed scratch array (per GPU). */
+size_t sr_force_static_capacity(void);
+
 /* Pair statistics for the same call shape as sr_force (no accelerations):
  *   *useful     : directed pairs (i, j), i != j, i not passive, with the
  *                 float32 s_ij < r_max^2 -- the interactions Eq. (force)

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "libsr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["sr_ctx.cpp", "sr_bin.hip", "sr_force.hip", "sr_split.hip", "sr_plan.cpp",
-           "sr_serve.cpp", "sr_pm.hip", "sr_step.cpp", "sr_tree.hip"]
+           "sr_serve.cpp", "sr_pm.hip", "sr_step.cpp", "sr_tree.hip", "sr_noalloc.hip"]
 
 # Device flags: gfx950 only; explicit fmaf everywhere, so no implicit
 # contraction; packed FP32 instructions are switched off in code generation.

@@ -133,6 +133,11 @@ extern "C" int sr_ctx_create(int device, void *hip_stream, size_t arena_bytes, s
         return SR_ENOMEM;
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    // device address of sr_force_static's fixed scratch on this device
+    if (static_scratch_setup(device) != SR_OK) {
+        delete ctx;
+        return SR_EDEVICE;
+    }
     void *p = nullptr;
     if (hipMalloc(&p, 256) != hipSuccess) {
         delete ctx;

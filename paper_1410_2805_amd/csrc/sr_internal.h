@@ -196,6 +196,10 @@ constexpr int kChunk2 = 128;       // ... and at two targets per lane (chaining-
 constexpr int kMaxSplit = 16;      // at most 16 lane groups share one target
 constexpr int kLptBlock = 1024;    // items per block of the cost-bucket sort
 
+// Looks up the device address of sr_force_static's fixed scratch array on
+// `device` (current) once (sr_noalloc.hip).
+int static_scratch_setup(int device);
+
 // Host helpers (sr_ctx.cpp)
 int sr_fail(sr_ctx *ctx, int code, const char *fmt, ...);
 int sr_make_geom(sr_ctx *ctx, const sr_box *box, double cell, Geom *g, int xsplit = 1);

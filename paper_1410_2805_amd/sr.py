@@ -125,6 +125,9 @@ def _load():
         "sr_scratch_bytes": (ctypes.c_int, [BP, f64, i64, ctypes.c_int, ctypes.POINTER(sz)]),
         "sr_bin": (ctypes.c_int, [P, P, P, P, i64, BP, f64, P, P]),
         "sr_force": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, f32, f32, P, P, P, P, P]),
+        "sr_force_static": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, f32, f32, P, P, P, P,
+                                           P]),
+        "sr_force_static_capacity": (sz, []),
         "sr_pair_stats": (ctypes.c_int, [P, P, P, P, i64, BP, f64, f32, P,
                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "sr_timing_enable": (ctypes.c_int, [P, ctypes.c_int]),
@@ -192,7 +195,7 @@ def exported_symbols() -> list[str]:
             "sr_server_cancel", "sr_server_info_get", "sr_server_destroy",
             "sr_pm_create", "sr_pm_destroy", "sr_pm_bytes", "sr_pm_deposit", "sr_pm_fft",
             "sr_pm_force", "sr_pm_force_split", "sr_ksk_step", "sr_force_tree",
-            "sr_tree_leaves", "sr_kinetic"]
+            "sr_tree_leaves", "sr_kinetic", "sr_force_static", "sr_force_static_capacity"]
 
 
 def _ptr(t):
@@ -333,6 +336,30 @@ def sr_force(ctx: Context, x, y, z, m, box: Box, cell: float, r_max: float, eps:
                             float(eps), c, _f32(ax, n, "ax"), _f32(ay, n, "ay"),
                             _f32(az, n, "az"), _ptr(mom)))
     return ax, ay, az, mom
+
+
+def sr_force_static(ctx: Context, x, y, z, m, box: Box, cell: float, r_max: float, eps: float,
+                    poly, out, momentum=None):
+    """sr_force with the library's fixed scratch array: the outputs (ax, ay,
+    az) and the optional float64[3] momentum are caller-allocated tensors,
+    and the call allocates nothing.  Returns (ax, ay, az, momentum)."""
+    n = int(x.shape[0])
+    ax, ay, az = out
+    if momentum is not None and not (momentum.is_cuda and momentum.dtype == torch.float64
+                                     and momentum.numel() == 3 and momentum.is_contiguous()):
+        raise ValueError("momentum must be a contiguous float64[3] CUDA tensor")
+    c = (ctypes.c_float * 6)(*[float(v) for v in poly])
+    ctx._bind_stream()
+    ctx._check(lib.sr_force_static(ctx._h, _f32(x, n, "x"), _f32(y, n, "y"), _f32(z, n, "z"),
+                                   _f32(m, n, "mass"), n, ctypes.byref(box), float(cell),
+                                   float(r_max), float(eps), c, _f32(ax, n, "ax"),
+                                   _f32(ay, n, "ay"), _f32(az, n, "az"), _ptr(momentum)))
+    return ax, ay, az, momentum
+
+
+def sr_force_static_capacity() -> int:
+    """Bytes of the fixed scratch array sr_force_static uses (per GPU)."""
+    return int(lib.sr_force_static_capacity())
 
 
 def _typed(t, n, dtype, name):

@@ -1,0 +1,71 @@
+"""sr_force_static (fixed device scratch, no allocation) against sr_force and
+the FP64 oracle, through the C ABI: two calls in a row on one GPU, the second
+with a smaller box, each bitwise equal to sr_force at the same tuning."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1410_2805_amd import gridfit
+from paper_1410_2805_amd import workloads as W
+from tests.parity import accel_np, check_accel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+R_MAX, EPS = 3.0, 0.1
+
+
+def _static_and_plain(S, ctx, p, poly, cell=3.0):
+    t = to_dev(p)
+    box = S.Box.make(p.L, periodic=p.periodic, skin=p.skin)
+    dev = t["x"].device
+    out = tuple(torch.full((p.n,), float("nan"), dtype=torch.float32, device=dev)
+                for _ in range(3))
+    mom = torch.full((3,), float("nan"), dtype=torch.float64, device=dev)
+    S.sr_force_static(ctx, t["x"], t["y"], t["z"], t["m"], box, cell, R_MAX, EPS, poly,
+                      out=out, momentum=mom)
+    ctx.sync()
+    a_static = accel_np(*out)
+    m_static = mom.cpu().numpy()
+    ax, ay, az, m_plain = S.sr_force(ctx, t["x"], t["y"], t["z"], t["m"], box, cell, R_MAX, EPS,
+                                     poly, momentum=True)
+    ctx.sync()
+    return a_static, m_static, accel_np(ax, ay, az), m_plain.cpu().numpy()
+
+
+def test_static_scratch_matches_sr_force():
+    from paper_1410_2805_amd import sr as S
+    poly = gridfit.poly_coeffs()
+    ctx = S.Context(0)
+    try:
+        # a periodic box, then a smaller clustered open box with a skin
+        cases = [W.uniform(110_592, 48.0, 11), W.nfw_share(8000, 20.0, 12, skin=3.0)]
+        for p in cases:
+            print("case: n=%d L=%g periodic=%s" % (p.n, p.L, p.periodic), flush=True)
+            a_s, m_s, a_p, m_p = _static_and_plain(S, ctx, p, poly)
+            assert np.array_equal(a_s, a_p), "sr_force_static differs from sr_force"
+            assert np.array_equal(m_s, m_p), "momentum differs from sr_force"
+            tg = np.sort(np.random.default_rng(5).choice(p.n, min(p.n, 2048), replace=False))
+            ref = O.force(p.x, p.y, p.z, p.m, p.L, R_MAX, EPS, poly.astype(np.float64),
+                          periodic=p.periodic, skin=p.skin, targets=tg)
+            check_accel(a_s[tg], ref, "static n=%d" % p.n)
+    finally:
+        ctx.close()
+
+
+def test_static_scratch_too_large_is_refused():
+    from paper_1410_2805_amd import sr as S
+    poly = gridfit.poly_coeffs()
+    ctx = S.Context(0)
+    try:
+        n = 4_000_000  # about 160 MB of scratch: beyond the fixed array
+        assert S.sr_force_static_capacity() < 40 * n
+        dev = torch.device("cuda:0")
+        x = torch.full((n,), 1.0, dtype=torch.float32, device=dev)
+        out = tuple(torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
+        box = S.Box.make(160.0)
+        with pytest.raises(S.SRError) as e:
+            S.sr_force_static(ctx, x, x, x, x, box, 3.0, R_MAX, EPS, poly, out=out)
+        assert "scratch" in str(e.value)
+    finally:
+        ctx.close()
