@@ -128,12 +128,31 @@ __device__ __forceinline__ int particle_cell(const Batch &B, int i, int *status)
     return d.cbase + c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
 }
 
+// LDS hash slot of cell id `id` (inserted when absent): at most 1024 keys in
+// 2048 slots, so the linear probe always ends.
+__device__ __forceinline__ int hash_slot(int *hkey, int id)
+{
+    int h = (int)(((unsigned)id * 2654435761u) >> 21) & (kHash - 1);
+    for (;;) {
+        const int old = atomicCAS(&hkey[h], -1, id);
+        if (old == -1 || old == id)
+            return h;
+        h = (h + 1) & (kHash - 1);
+    }
+}
+
+constexpr int kPeelMax = 8;    // lane groups of one cell served per wavefront pass
+constexpr int kPeelGroup = 4;  // ... while the groups found hold at least this many lanes
+
 // Cell ids and the histogram.  A block takes 1024 particles and first counts
-// them per cell in an LDS hash table (input that is even roughly spatially
-// ordered repeats cells a lot), then adds each distinct cell's count to the
-// global histogram with one atomic; a particle's arrival rank is its block's
-// base plus its rank inside the block (ranks are unordered; the per-cell sort
-// restores the stable order).
+// them per cell in an LDS hash table, then adds each distinct cell's count to
+// the global histogram with one atomic; a particle's arrival rank is its
+// block's base plus its rank inside the block (ranks are unordered; the
+// per-cell sort restores the stable order).  Clustered input puts many lanes
+// of a wavefront in one cell, and their LDS atomics on one address would
+// serialize: the lanes sharing the lowest remaining lane's cell are found by
+// one ballot and served by a single pair of LDS atomics for the whole group,
+// repeated while such groups are large; the remaining lanes go one by one.
 __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ cid,
                                                    int *__restrict__ slot,
                                                    int *__restrict__ count, int *__restrict__ status)
@@ -145,22 +164,44 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
         hcnt[h] = 0;
     }
     __syncthreads();
+    const int lane = threadIdx.x & 63;
     int hs[kCellidPer], rk[kCellidPer];
     const int base = blockIdx.x * kCellidBlock;
 #pragma unroll
     for (int k = 0; k < kCellidPer; ++k) {
         const int i = base + k * kBlock + threadIdx.x;
-        hs[k] = -1;
-        if (i < B.ntot) {
-            const int id = particle_cell(B, i, status);
+        const bool valid = i < B.ntot;
+        int id = -1;
+        if (valid) {
+            id = particle_cell(B, i, status);
             cid[i] = id;
-            int h = (int)(((unsigned)id * 2654435761u) >> 21) & (kHash - 1);
-            for (;;) {  // at most 1024 keys in 2048 slots: always terminates
-                const int old = atomicCAS(&hkey[h], -1, id);
-                if (old == -1 || old == id)
-                    break;
-                h = (h + 1) & (kHash - 1);
+        }
+        hs[k] = -1;
+        rk[k] = 0;
+        unsigned long long rem = __ballot(valid);
+        for (int it = 0; it < kPeelMax && rem; ++it) {
+            const int leader = __ffsll((long long)rem) - 1;
+            const int key = __builtin_amdgcn_readlane(id, leader);
+            const unsigned long long grp = __ballot(id == key) & rem;
+            const int gsize = __popcll(grp);
+            int hh = 0, hb = 0;
+            if (lane == leader) {
+                hh = hash_slot(hkey, key);
+                hb = atomicAdd(&hcnt[hh], gsize);
             }
+            hh = __builtin_amdgcn_readlane(hh, leader);
+            hb = __builtin_amdgcn_readlane(hb, leader);
+            if ((grp >> lane) & 1ull) {
+                hs[k] = hh;
+                rk[k] = hb + (int)__builtin_amdgcn_mbcnt_hi(
+                                 (unsigned)(grp >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)grp, 0u));
+            }
+            rem &= ~grp;
+            if (gsize < kPeelGroup)
+                break;
+        }
+        if ((rem >> lane) & 1ull) {
+            const int h = hash_slot(hkey, id);
             hs[k] = h;
             rk[k] = atomicAdd(&hcnt[h], 1);
         }
@@ -349,11 +390,33 @@ __global__ __launch_bounds__(kBlock) void k_cell_active(Batch B, const int *__re
 
 constexpr int kSegGroup = 4;  // consecutive cells per wavefront
 
+// Large cells are listed by size class, class c holding the cells of
+// kLargeCell 2^c + 1 .. kLargeCell 2^(c+1) particles (the last class: all
+// larger), so that the block sort can take them biggest first.  Class c's
+// list has room for every cell of more than kLargeCell 2^c particles of n.
+constexpr int kLargeClasses = 8;
+__host__ __device__ inline int large_class_cap(int64_t n, int c)
+{
+    return (int)(n / ((int64_t)kLargeCell << c) + 1);
+}
+__host__ __device__ inline int large_class_base(int64_t n, int c)
+{
+    int b = 0;
+    for (int k = 0; k < c; ++k)
+        b += large_class_cap(n, k);
+    return b;
+}
+__device__ __forceinline__ int large_class(int len)
+{
+    const int c = 31 - __clz(len - 1) - 10;  // len > kLargeCell = 2^10
+    return c < kLargeClasses - 1 ? c : kLargeClasses - 1;
+}
+
 // Sorts one cell's slots [b, b + len) by one wavefront (len <= kLargeCell;
 // larger cells are queued for k_segsort_large).
 __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int *sb,
                           int *__restrict__ large_list, int *__restrict__ large_count,
-                          int *__restrict__ inv, int lane)
+                          int *__restrict__ inv, int lane, int ntot)
 {
     if (len <= 32) {
         // small cell: each index's rank is the number of smaller ones
@@ -390,8 +453,9 @@ __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int 
         }
         wave_sync();
     } else if (lane == 0) {
-        int k = atomicAdd(large_count, 1);
-        large_list[k] = cell;
+        const int c = large_class(len);
+        const int k = atomicAdd(&large_count[c], 1);
+        large_list[large_class_base(ntot, c) + k] = cell;
     }
 }
 
@@ -462,30 +526,148 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
     }
     for (int k = 0; k < nc; ++k)
         sort_cell(c0 + k, bounds[k], bounds[k + 1] - bounds[k], perm, buf[wid], large_list,
-                  large_count, inv, lane);
+                  large_count, inv, lane, B.ntot);
 }
 
-// Block-level sort of one large cell: LDS-sorted runs of kLargeCell, then
-// merge rounds in which every element finds its output slot from its rank in
-// the partner run (values are distinct original indices).  The rank is a
-// binary search in global memory, a chain of dependent loads; the block is
-// kLargeBlock threads wide so that more of them are in flight per round.
 constexpr int kLargeBlock = 1024;
 constexpr int kMergeIlp = 4;
+constexpr int kMergeSeg = 16;                   // merge outputs per thread segment
+// indices a block sorts in LDS: 160 KiB less 256 bytes of static LDS
+constexpr int kLdsCell = 40896;
+
+// Sorts the indices buf[0, len) of one cell ascending (len <= kLdsCell, whole
+// block) and returns where the sorted indices lie (buf, or buf + P when the
+// last merge round wrote the second half).  Runs of 64 are sorted in
+// registers by bitonic networks, one per wavefront; then merge rounds in
+// which each entry's new slot is its offset in its run plus its rank among
+// the partner run's entries (a binary search; the indices are distinct).  A
+// round writes every entry to its new slot in a second buffer -- the other
+// half of LDS when the cell fits twice, else the cell's global scratch `out`,
+// read back after the round -- so no entry moves while others still search.
+// The tail up to whole runs holds INT_MAX, which sorts last and stays put.
+__device__ int *lds_sort_cell(int *buf, int len, int *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int P = (len + 63) & ~63;
+    const bool twice = 2 * P <= kLdsCell;
+    // a wavefront's 64 lanes hold the whole run (P is a multiple of 64)
+    for (int e = threadIdx.x; e < P; e += kLargeBlock) {
+        int v = e < len ? buf[e] : INT_MAX;
+        v = bitonic64(v, lane);
+        buf[e] = v;
+        if (twice)
+            buf[P + e] = INT_MAX;
+    }
+    __syncthreads();
+    int *src = buf;
+    int *dst = twice ? buf + P : out;
+    for (int w = 64; w < P; w <<= 1) {
+        // merge path: thread segments of kMergeSeg outputs (kMergeSeg divides
+        // 2w, so a segment stays inside one pair of runs); each finds where
+        // its first output splits the two runs by one binary search along its
+        // diagonal, then merges sequentially
+        for (int o = threadIdx.x * kMergeSeg; o < P; o += kLargeBlock * kMergeSeg) {
+            const int p0 = o & ~(2 * w - 1);
+            const int d = o - p0;
+            const int *A = src + p0;
+            const int lenA = P - p0 < w ? P - p0 : w;
+            const int *Bv = A + lenA;
+            const int lenB = P - p0 - lenA < w ? P - p0 - lenA : w;
+            int lo = d - lenB > 0 ? d - lenB : 0;
+            int hi = d < lenA ? d : lenA;
+            while (lo < hi) {
+                const int m = (lo + hi) >> 1;
+                if (A[m] < Bv[d - 1 - m])
+                    lo = m + 1;
+                else
+                    hi = m;
+            }
+            int i = lo, j = d - lo;
+            int a = i < lenA ? A[i] : INT_MAX;
+            int b = j < lenB ? Bv[j] : INT_MAX;
+            for (int k = 0; k < kMergeSeg; ++k) {
+                const bool take_a = j >= lenB || (i < lenA && a < b);
+                const int v = take_a ? a : b;
+                // the global scratch covers the cell's len entries only; the
+                // padding (largest) lands past them
+                if (twice || o + k < len)
+                    dst[o + k] = v;
+                if (take_a) {
+                    ++i;
+                    a = i < lenA ? A[i] : INT_MAX;
+                } else {
+                    ++j;
+                    b = j < lenB ? Bv[j] : INT_MAX;
+                }
+            }
+        }
+        __syncthreads();
+        if (twice) {
+            int *t = src;
+            src = dst;
+            dst = t;
+        } else {
+            for (int e = threadIdx.x; e < len; e += kLargeBlock)
+                buf[e] = out[e];
+            __syncthreads();
+        }
+    }
+    return src;
+}
+
+// Block-level sort of one large cell.  Cells of at most kLdsCell indices are
+// sorted entirely in LDS (lds_sort_cell).  Larger ones: LDS-sorted runs of
+// kLargeCell, then merge rounds in which every element finds its output slot
+// from its rank in the partner run (values are distinct original indices), a
+// binary search in global memory; the block is kLargeBlock threads wide so
+// that more of those dependent loads are in flight per round.
 __global__ __launch_bounds__(kLargeBlock) void k_segsort_large(Batch B,
                                                           const int *__restrict__ offsets,
                                                           int *__restrict__ perm,
                                                           int *__restrict__ tmp,
                                                           const int *__restrict__ large_list,
-                                                          const int *__restrict__ large_count,
+                                                          int *__restrict__ large_count,
                                                           int *__restrict__ inv)
 {
-    __shared__ int buf[kLargeCell];
-    const int nl = *large_count;
-    for (int li = blockIdx.x; li < nl; li += gridDim.x) {
-        const int cell = large_list[li];
+    extern __shared__ int buf[];  // kLdsCell entries
+    __shared__ int next;
+    int cnt[kLargeClasses];
+#pragma unroll
+    for (int c = 0; c < kLargeClasses; ++c)
+        cnt[c] = large_count[c];
+    for (;;) {
+        // the next cell, biggest class first (large_count[kLargeClasses] is
+        // the work counter)
+        if (threadIdx.x == 0)
+            next = atomicAdd(&large_count[kLargeClasses], 1);
+        __syncthreads();
+        int w = next;
+        __syncthreads();
+        int cell = -1;
+        for (int c = kLargeClasses - 1; c >= 0; --c) {
+            if (w < cnt[c]) {
+                cell = large_list[large_class_base(B.ntot, c) + w];
+                break;
+            }
+            w -= cnt[c];
+        }
+        if (cell < 0)
+            break;
         const int b = offsets[cell];
         const int len = offsets[cell + 1] - b;
+        if (len <= kLdsCell) {
+            for (int e = threadIdx.x; e < len; e += kLargeBlock)
+                buf[e] = perm[b + e];
+            const int *sorted_idx = lds_sort_cell(buf, len, tmp + b);
+            for (int e = threadIdx.x; e < len; e += kLargeBlock) {
+                const int v = sorted_idx[e];
+                perm[b + e] = v;
+                if (inv)
+                    inv[v] = b + e;
+            }
+            __syncthreads();
+            continue;
+        }
         // 1) sort runs of kLargeCell in LDS (bitonic, whole block)
         for (int r0 = 0; r0 < len; r0 += kLargeCell) {
             int rl = len - r0 < kLargeCell ? len - r0 : kLargeCell;
@@ -647,8 +829,8 @@ void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
     s.count = b.take<int>((size_t)ctot);
     scan_layout(b, (int)ctot, &s.scan_part);
     s.tmp = b.take<int>(nn);
-    s.large_list = b.take<int>(nn / (kLargeCell + 1) + 1);
-    s.large_count = b.take<int>(1);
+    s.large_list = b.take<int>((size_t)large_class_base((int64_t)nn, kLargeClasses));
+    s.large_count = b.take<int>(kLargeClasses + 1);
     s.mass_mixed = b.take<int>((size_t)(nb > 0 ? nb : 1));
     s.scan_flag = b.take<int>(1);
     s.lpt = b.take<int>(64);
@@ -666,7 +848,7 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
         cl.p[0] = s.count;
         cl.n[0] = B.ctot;
         cl.p[1] = s.large_count;
-        cl.n[1] = 1;
+        cl.n[1] = kLargeClasses + 1;
         cl.p[2] = s.mass_mixed;
         cl.n[2] = B.nb;
         cl.p[3] = s.scan_flag;
@@ -713,10 +895,18 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
     if ((rc = sr_check_launch(ctx, "k_segsort")))
         return rc;
     if (n > kLargeCell) {
+        // one block per CU, each with the whole LDS (kLdsCell indices)
+        static const hipError_t lds_ok = hipFuncSetAttribute(
+            (const void *)k_segsort_large, hipFuncAttributeMaxDynamicSharedMemorySize,
+            kLdsCell * (int)sizeof(int));
+        if (lds_ok != hipSuccess)
+            return sr_fail(ctx, SR_EDEVICE, "k_segsort_large: %d bytes of LDS not available",
+                           kLdsCell * (int)sizeof(int));
         int max_large = n / (kLargeCell + 1) + 1;
-        int grid = max_large < 512 ? max_large : 512;
-        hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kLargeBlock), 0, ctx->stream, B,
-                           offsets, perm, s.tmp, s.large_list, s.large_count, inv);
+        int grid = max_large < 256 ? max_large : 256;
+        hipLaunchKernelGGL(k_segsort_large, dim3(grid), dim3(kLargeBlock),
+                           kLdsCell * sizeof(int), ctx->stream, B, offsets, perm, s.tmp,
+                           s.large_list, s.large_count, inv);
         if ((rc = sr_check_launch(ctx, "k_segsort_large")))
             return rc;
     }

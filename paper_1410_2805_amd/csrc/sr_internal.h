@@ -160,8 +160,8 @@ struct BinScratch {
     int *count;       // [ctot] particles per cell
     int *scan_part;   // [scan tiles] partial sums
     int *tmp;         // [ntot] ping-pong buffer of the large-cell merge
-    int *large_list;  // [max_large] cells too big for one wavefront's LDS
-    int *large_count; // [1]
+    int *large_list;  // cells too big for one wavefront's LDS, by size class
+    int *large_count; // [9] large cells per size class, then the block sort's work counter
     int *mass_mixed;  // [nb] box b: 1 if any of its masses differs from its first
     int *scan_flag;   // [1] last-block counter of the scans (kept at 0)
     int *lpt;         // [64] key totals and cursors of the longest-first item order

@@ -44,10 +44,11 @@ def test_uniform_32k(sr, ctx):
     _assert_same(*_bin_both(sr, ctx, p.x, p.y, p.z, 32.0, 3.0))
 
 
-@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 1000, 1024, 1025, 3000, 70000])
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 1000, 1024, 1025, 3000, 40896, 40897, 70000])
 def test_one_cell_sizes(sr, ctx, n):
     """Every particle in one cell: exercises the register, LDS and
-    multi-run merge paths of the per-cell sort."""
+    multi-run merge paths of the per-cell sort (a whole-block sort in LDS up
+    to 40896 particles, runs merged through global memory beyond)."""
     rng = np.random.default_rng(n)
     x = (rng.random(n) * 2.9).astype(np.float32)
     y = (3.0 + rng.random(n) * 2.9).astype(np.float32)
@@ -66,6 +67,20 @@ def test_mixed_cell_sizes(sr, ctx):
     pos = np.concatenate(pts)
     pos = pos[rng.permutation(pos.shape[0])].astype(np.float32)
     _assert_same(*_bin_both(sr, ctx, pos[:, 0], pos[:, 1], pos[:, 2], 15.0, 3.0))
+
+
+def test_large_cells_side_by_side(sr, ctx):
+    """Several cells of 1025..50000 particles in one box, random input order:
+    large cells sorted by different blocks, in LDS and through global memory."""
+    rng = np.random.default_rng(11)
+    sizes = [1025, 12000, 40896, 40897, 25000, 2049, 50000, 20480, 20481]
+    pts = []
+    for k, s in enumerate(sizes):
+        c = np.array([k % 4, (k // 4) % 4, k // 16], dtype=np.float64) * 3.0
+        pts.append(c + rng.random((s, 3)) * 2.999)
+    pos = np.concatenate(pts)
+    pos = pos[rng.permutation(pos.shape[0])].astype(np.float32)
+    _assert_same(*_bin_both(sr, ctx, pos[:, 0], pos[:, 1], pos[:, 2], 12.0, 3.0))
 
 
 def test_cell_edges_and_top(sr, ctx):
