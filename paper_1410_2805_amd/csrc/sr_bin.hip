@@ -81,7 +81,6 @@ __global__ void k_fill(int *__restrict__ p, int value, int64_t count)
 
 constexpr int kCellidPer = 4;                 // particles per thread
 constexpr int kCellidBlock = kBlock * kCellidPer;  // 1024 particles per block
-constexpr int kHash = 2048;                   // > 2 x distinct cells per block
 
 __device__ __forceinline__ int particle_cell(const Batch &B, int i, int *status)
 {
@@ -128,19 +127,6 @@ __device__ __forceinline__ int particle_cell(const Batch &B, int i, int *status)
     return d.cbase + c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
 }
 
-// LDS hash slot of cell id `id` (inserted when absent): at most 1024 keys in
-// 2048 slots, so the linear probe always ends.
-__device__ __forceinline__ int hash_slot(int *hkey, int id)
-{
-    int h = (int)(((unsigned)id * 2654435761u) >> 21) & (kHash - 1);
-    for (;;) {
-        const int old = atomicCAS(&hkey[h], -1, id);
-        if (old == -1 || old == id)
-            return h;
-        h = (h + 1) & (kHash - 1);
-    }
-}
-
 constexpr int kPeelMax = 8;    // lane groups of one cell served per wavefront pass
 constexpr int kPeelGroup = 4;  // ... while the groups found hold at least this many lanes
 
@@ -153,9 +139,15 @@ constexpr int kPeelGroup = 4;  // ... while the groups found hold at least this 
 // serialize: the lanes sharing the lowest remaining lane's cell are found by
 // one ballot and served by a single pair of LDS atomics for the whole group,
 // repeated while such groups are large; the remaining lanes go one by one.
+//
+// With an activity mask (kMasked; flag cleared) the pass also leaves in
+// flag[cell] the largest activity value of the cell's particles (1, or 2 for
+// cells cut into finer work items; 0: no active particle).
+template <bool kMasked>
 __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ cid,
                                                    int *__restrict__ slot,
-                                                   int *__restrict__ count, int *__restrict__ status)
+                                                   int *__restrict__ count, int *__restrict__ status,
+                                                   int *__restrict__ flag)
 {
     __shared__ int hkey[kHash];
     __shared__ int hcnt[kHash];
@@ -175,6 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
         if (valid) {
             id = particle_cell(B, i, status);
             cid[i] = id;
+            if (kMasked) {
+                const BoxDesc &d = box_at(B, find_box(B.pstart, B.nb, i));
+                const int v = d.active ? d.active[i - d.pbase] : 1;
+                if (v && flag[id] < v)  // the read only saves atomics; the maximum decides
+                    atomicMax(&flag[id], v);
+            }
         }
         hs[k] = -1;
         rk[k] = 0;
@@ -186,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
             const int gsize = __popcll(grp);
             int hh = 0, hb = 0;
             if (lane == leader) {
-                hh = hash_slot(hkey, key);
+                hh = lds_hash_slot(hkey, key);
                 hb = atomicAdd(&hcnt[hh], gsize);
             }
             hh = __builtin_amdgcn_readlane(hh, leader);
@@ -201,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
                 break;
         }
         if ((rem >> lane) & 1ull) {
-            const int h = hash_slot(hkey, id);
+            const int h = lds_hash_slot(hkey, id);
             hs[k] = h;
             rk[k] = atomicAdd(&hcnt[h], 1);
         }
@@ -311,26 +309,6 @@ __device__ __forceinline__ int bitonic64(int v, int lane)
     return v;
 }
 
-// Bitonic sort of P (power of two, <= 1024) ints in LDS by one wavefront.
-__device__ void lds_bitonic(int *buf, int P, int lane)
-{
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = lane; t < P / 2; t += 64) {
-                int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                int l = i + j;
-                bool up = (i & k) == 0;
-                int a = buf[i], c = buf[l];
-                if ((a > c) == up) {
-                    buf[i] = c;
-                    buf[l] = a;
-                }
-            }
-            wave_sync();
-        }
-    }
-}
-
 __device__ __forceinline__ float4 gather_one(const BoxDesc &d, int v)
 {
     const int li = v - d.pbase;
@@ -375,20 +353,52 @@ __global__ __launch_bounds__(kBlock) void k_gather(Batch B, const int *__restric
     }
 }
 
-// Activity mask: flag[cell] = 1 for every cell holding an active particle
-// (the flags were cleared; equal plain stores need no atomics).
-__global__ __launch_bounds__(kBlock) void k_cell_active(Batch B, const int *__restrict__ cid,
-                                                        int *__restrict__ flag)
+constexpr int kMergeSeg = 16;  // merge outputs per thread segment
+
+// One segment of a merge round over runs of w sorted ints (src[0, P), P a
+// multiple of 64, runs [p0, p0 + w) and [p0 + w, p0 + 2w) merged in pairs):
+// the kMergeSeg outputs from position o (kMergeSeg divides 2w, so the segment
+// stays inside one pair).  Merge path: one binary search along the segment's
+// diagonal finds how many of its predecessors come from each run, then a
+// sequential merge.  Values are distinct except the INT_MAX padding, which
+// only the last run holds.
+__device__ __forceinline__ void merge_segment(const int *src, int P, int w, int o,
+                                              int (&out)[kMergeSeg])
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= B.ntot)
-        return;
-    const BoxDesc &d = box_at(B, find_box(B.pstart, B.nb, i));
-    if (!d.active || d.active[i - d.pbase])
-        flag[cid[i]] = 1;
+    const int p0 = o & ~(2 * w - 1);
+    const int d = o - p0;
+    const int *A = src + p0;
+    const int lenA = P - p0 < w ? P - p0 : w;
+    const int *Bv = A + lenA;
+    const int lenB = P - p0 - lenA < w ? P - p0 - lenA : w;
+    int lo = d - lenB > 0 ? d - lenB : 0;
+    int hi = d < lenA ? d : lenA;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (A[m] < Bv[d - 1 - m])
+            lo = m + 1;
+        else
+            hi = m;
+    }
+    int i = lo, j = d - lo;
+    int a = i < lenA ? A[i] : INT_MAX;
+    int b = j < lenB ? Bv[j] : INT_MAX;
+#pragma unroll
+    for (int k = 0; k < kMergeSeg; ++k) {
+        const bool take_a = j >= lenB || (i < lenA && a < b);
+        out[k] = take_a ? a : b;
+        if (take_a) {
+            ++i;
+            a = i < lenA ? A[i] : INT_MAX;
+        } else {
+            ++j;
+            b = j < lenB ? Bv[j] : INT_MAX;
+        }
+    }
 }
 
 constexpr int kSegGroup = 4;  // consecutive cells per wavefront
+constexpr int kFineChunk = 32;  // targets per item in cells flagged for finer items
 
 // Large cells are listed by size class, class c holding the cells of
 // kLargeCell 2^c + 1 .. kLargeCell 2^(c+1) particles (the last class: all
@@ -438,13 +448,29 @@ __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int 
                 inv[v] = b + lane;
         }
     } else if (len <= kLargeCell) {
-        int P = 128;
-        while (P < len)
-            P <<= 1;
-        for (int t = lane; t < P; t += 64)
-            sb[t] = t < len ? perm[b + t] : INT_MAX;
+        // runs of 64 sorted in registers, then merge rounds in which each
+        // lane takes one segment of kMergeSeg outputs (64 kMergeSeg =
+        // kLargeCell), held in registers until every lane has read the round
+        const int P = (len + 63) & ~63;
+        for (int r = 0; r < P; r += 64) {
+            int v = r + lane < len ? perm[b + r + lane] : INT_MAX;
+            v = bitonic64(v, lane);
+            sb[r + lane] = v;
+        }
         wave_sync();
-        lds_bitonic(sb, P, lane);
+        const int o = lane * kMergeSeg;
+        for (int w = 64; w < P; w <<= 1) {
+            int v[kMergeSeg];
+            if (o < P)
+                merge_segment(sb, P, w, o, v);
+            wave_sync();
+            if (o < P) {
+#pragma unroll
+                for (int k = 0; k < kMergeSeg; ++k)
+                    sb[o + k] = v[k];
+            }
+            wave_sync();
+        }
         for (int t = lane; t < len; t += 64) {
             int v = sb[t];
             perm[b + t] = v;
@@ -480,11 +506,15 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
     const int nc = B.ctot - c0 < kSegGroup ? B.ctot - c0 : kSegGroup;
     if (chunk_count && lane < nc) {
         const int c = c0 + lane;
-        int q = mesh_chunks_for(offsets[c + 1] - offsets[c]);
-        // an activity mask drops the cells without an active particle
-        // (k_cell_active left 1 in chunk_count for the others)
-        if (q && box_at(B, find_box(B.cstart, B.nb, c)).active)
-            q = chunk_count[c] ? q : 0;
+        const int len = offsets[c + 1] - offsets[c];
+        int q = mesh_chunks(len);
+        // an activity mask drops the cells without an active particle and
+        // cuts those flagged 2 into items of at most kFineChunk targets
+        // (k_cellid left the flags in chunk_count)
+        if (q && box_at(B, find_box(B.cstart, B.nb, c)).active) {
+            const int f = chunk_count[c];
+            q = f == 0 ? 0 : (f >= 2 ? (len + kFineChunk - 1) / kFineChunk : q);
+        }
         chunk_count[c] = q;
     }
     int bounds[kSegGroup + 1];
@@ -531,7 +561,6 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
 
 constexpr int kLargeBlock = 1024;
 constexpr int kMergeIlp = 4;
-constexpr int kMergeSeg = 16;                   // merge outputs per thread segment
 // indices a block sorts in LDS: 160 KiB less 256 bytes of static LDS
 constexpr int kLdsCell = 40896;
 
@@ -562,44 +591,15 @@ __device__ int *lds_sort_cell(int *buf, int len, int *__restrict__ out)
     int *src = buf;
     int *dst = twice ? buf + P : out;
     for (int w = 64; w < P; w <<= 1) {
-        // merge path: thread segments of kMergeSeg outputs (kMergeSeg divides
-        // 2w, so a segment stays inside one pair of runs); each finds where
-        // its first output splits the two runs by one binary search along its
-        // diagonal, then merges sequentially
         for (int o = threadIdx.x * kMergeSeg; o < P; o += kLargeBlock * kMergeSeg) {
-            const int p0 = o & ~(2 * w - 1);
-            const int d = o - p0;
-            const int *A = src + p0;
-            const int lenA = P - p0 < w ? P - p0 : w;
-            const int *Bv = A + lenA;
-            const int lenB = P - p0 - lenA < w ? P - p0 - lenA : w;
-            int lo = d - lenB > 0 ? d - lenB : 0;
-            int hi = d < lenA ? d : lenA;
-            while (lo < hi) {
-                const int m = (lo + hi) >> 1;
-                if (A[m] < Bv[d - 1 - m])
-                    lo = m + 1;
-                else
-                    hi = m;
-            }
-            int i = lo, j = d - lo;
-            int a = i < lenA ? A[i] : INT_MAX;
-            int b = j < lenB ? Bv[j] : INT_MAX;
-            for (int k = 0; k < kMergeSeg; ++k) {
-                const bool take_a = j >= lenB || (i < lenA && a < b);
-                const int v = take_a ? a : b;
-                // the global scratch covers the cell's len entries only; the
-                // padding (largest) lands past them
+            int v[kMergeSeg];
+            merge_segment(src, P, w, o, v);
+            // the global scratch covers the cell's len entries only; the
+            // padding (largest) lands past them
+#pragma unroll
+            for (int k = 0; k < kMergeSeg; ++k)
                 if (twice || o + k < len)
-                    dst[o + k] = v;
-                if (take_a) {
-                    ++i;
-                    a = i < lenA ? A[i] : INT_MAX;
-                } else {
-                    ++j;
-                    b = j < lenB ? Bv[j] : INT_MAX;
-                }
-            }
+                    dst[o + k] = v[k];
         }
         __syncthreads();
         if (twice) {
@@ -861,23 +861,21 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
             return rc;
     }
     const int n = B.ntot;
+    // only single-box passes carry an activity mask (the batched forms pass
+    // none); its cell flags go to chunk_count, which k_segsort then turns
+    // into item counts
+    const bool masked = !B.boxes && B.one.active != nullptr && chunk_count;
+    if (masked && (rc = fill_enqueue(ctx, chunk_count, 0, B.ctot)))
+        return rc;
     if (n > 0) {
-        hipLaunchKernelGGL(k_cellid, dim3(blocks_for(n, kCellidBlock)), dim3(kBlock), 0,
-                           ctx->stream, B, s.cid, s.slot, s.count, ctx->status);
+        if (masked)
+            hipLaunchKernelGGL(k_cellid<true>, dim3(blocks_for(n, kCellidBlock)), dim3(kBlock), 0,
+                               ctx->stream, B, s.cid, s.slot, s.count, ctx->status, chunk_count);
+        else
+            hipLaunchKernelGGL(k_cellid<false>, dim3(blocks_for(n, kCellidBlock)), dim3(kBlock),
+                               0, ctx->stream, B, s.cid, s.slot, s.count, ctx->status, nullptr);
         if ((rc = sr_check_launch(ctx, "k_cellid")))
             return rc;
-    }
-    // only single-box passes carry an activity mask (the batched forms pass none)
-    const bool masked = !B.boxes && B.one.active != nullptr;
-    if (masked && chunk_count) {
-        if ((rc = fill_enqueue(ctx, chunk_count, 0, B.ctot)))
-            return rc;
-        if (n > 0) {
-            hipLaunchKernelGGL(k_cell_active, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0,
-                               ctx->stream, B, s.cid, chunk_count);
-            if ((rc = sr_check_launch(ctx, "k_cell_active")))
-                return rc;
-        }
     }
     if ((rc = scan_enqueue(ctx, s.count, B.ctot, s.scan_part, offsets, s.scan_flag)))
         return rc;

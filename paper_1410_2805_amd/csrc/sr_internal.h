@@ -89,7 +89,7 @@ struct BoxDesc {
     int pbase, n, cbase, _pad;
     const float *x, *y, *z, *m;   // positions, or cell offsets when g.split
     const int *cell3;             // split coordinates: packed chaining cells
-    const unsigned char *active;  // optional: only cells holding an active particle get items
+    const unsigned char *active;  // optional: 0 inactive, 1 active, 2 active in a cell cut into finer items; only cells holding an active particle get items
     float *ax, *ay, *az;
 };
 
@@ -125,6 +125,21 @@ __device__ __forceinline__ int find_box(const int *start, int nb, int v)
 __device__ __forceinline__ const BoxDesc &box_at(const Batch &B, int b)
 {
     return B.boxes ? B.boxes[b] : B.one;
+}
+
+// LDS hash table of a block's distinct cell ids: kHash slots for at most
+// 1024 keys, so the linear probe always ends.  Returns the slot of `id`,
+// inserting it when absent (hkey slots start at -1).
+constexpr int kHash = 2048;
+__device__ __forceinline__ int lds_hash_slot(int *hkey, int id)
+{
+    int h = (int)(((unsigned)id * 2654435761u) >> 21) & (kHash - 1);
+    for (;;) {
+        const int old = atomicCAS(&hkey[h], -1, id);
+        if (old == -1 || old == id)
+            return h;
+        h = (h + 1) & (kHash - 1);
+    }
 }
 
 // Scalars of the pair loop in the form the kernel evaluates.
@@ -246,7 +261,7 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
 
 // A force work item with nt targets gives each target S = floor(64/nt)
 // lanes (capped), which take disjoint slices of every source tile.
-__host__ __device__ inline int split_for(int nt)
+__host__ __device__ constexpr inline int split_for(int nt)
 {
     int s = nt > 0 ? 64 / nt : kMaxSplit;
     return s < 1 ? 1 : (s > kMaxSplit ? kMaxSplit : s);
@@ -259,7 +274,7 @@ __host__ __device__ inline int split_for(int nt)
 // covers targets [k n / q, (k + 1) n / q).  The count never exceeds
 // max(ceil(n / 64), n / 16), which bounds the items by (non-empty cells) +
 // n / 16.
-__host__ __device__ inline int chunks_for(int n)
+__host__ __device__ constexpr inline int chunks_for(int n)
 {
     if (n <= 0)
         return 0;
@@ -293,7 +308,7 @@ constexpr float kTwoPerLane = 2.0f;
 // targets per lane (1, or 2 with lane t holding targets t and t + ceil(nt/2))
 // and S lane groups, whichever needs fewer issue slots per source; returns
 // that cost in full-wavefront passes per source.
-__host__ __device__ inline float item_shape(int nt, int *tpl, int *S)
+__host__ __device__ constexpr inline float item_shape(int nt, int *tpl, int *S)
 {
     const float c1 = nt <= kChunk ? 1.0f / (float)split_for(nt) : 3.0e38f;
     const int s2 = split_for((nt + 1) / 2);
@@ -312,7 +327,7 @@ __host__ __device__ inline float item_shape(int nt, int *tpl, int *S)
 // lane: up to 256 targets the cheapest count under the same model with
 // item_shape's cost; beyond, chunks of at most kChunk2.  The count never
 // exceeds max(ceil(n / 64), n / 16) either.
-__host__ __device__ inline int mesh_chunks_for(int n)
+__host__ __device__ constexpr inline int mesh_chunks_for(int n)
 {
     if (n <= 0)
         return 0;
@@ -334,6 +349,37 @@ __host__ __device__ inline int mesh_chunks_for(int n)
         }
     }
     return bq;
+}
+
+// chunks_for and mesh_chunks_for of every n <= 4 kChunk, evaluated at compile
+// time: the device takes one lookup instead of the cost model's loops.
+struct ChunkTables {
+    unsigned char tree[4 * kChunk + 1];
+    unsigned char mesh[4 * kChunk + 1];
+};
+
+constexpr ChunkTables make_chunk_tables()
+{
+    ChunkTables t{};
+    for (int n = 0; n <= 4 * kChunk; ++n) {
+        t.tree[n] = (unsigned char)chunks_for(n);
+        t.mesh[n] = (unsigned char)mesh_chunks_for(n);
+    }
+    return t;
+}
+
+namespace {
+__constant__ const ChunkTables kChunkTab = make_chunk_tables();
+}  // namespace
+
+__device__ __forceinline__ int tree_chunks(int n)
+{
+    return n <= 4 * kChunk ? (n > 0 ? kChunkTab.tree[n] : 0) : (n + kChunk - 1) / kChunk;
+}
+
+__device__ __forceinline__ int mesh_chunks(int n)
+{
+    return n <= 4 * kChunk ? (n > 0 ? kChunkTab.mesh[n] : 0) : (n + kChunk2 - 1) / kChunk2;
 }
 
 // Work items of cell c (global id), q of them, written at items[first ..

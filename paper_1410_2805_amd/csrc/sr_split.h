@@ -46,15 +46,17 @@ int kick_stream_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, flo
 // chaining-cell counts (counts: ncell ints of scratch).
 int ml_levels_enqueue(sr_ctx *ctx, const SplitGeom &sg, const int *cell3, int n, int *counts,
                       int d, int lmin, int lmax, unsigned char *level);
-// active[i] = 1 where level[i] kicks after stream piece m of M.
-int ml_active_enqueue(sr_ctx *ctx, const unsigned char *level, int n, int m, int M,
+// active[i] = 1 where level[i] kicks after stream piece m of M (2 when
+// level[i] > lmin: the pass cuts such particles' cells into finer items).
+int ml_active_enqueue(sr_ctx *ctx, const unsigned char *level, int n, int m, int M, int lmin,
                       unsigned char *active);
 // Kick the particles whose level kicks at m by a tau / level (a may be null),
-// then stream every particle by `stream` (0: none).
+// then stream every particle nstream times by `stream` (0: none), rounding
+// after each as separate pieces would.
 int ml_update_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
                       float *oz, float *vx, float *vy, float *vz, const float *ax,
                       const float *ay, const float *az, const unsigned char *level, int m, int M,
-                      double tau, double stream);
+                      double tau, double stream, int nstream);
 
 // FP64 K = sum m |v|^2 / 2 into *out (device); part: kRedBlocks doubles.
 int kinetic_enqueue(sr_ctx *ctx, const float *vx, const float *vy, const float *vz,

@@ -205,13 +205,31 @@ __device__ __forceinline__ int split_cell_index(int packed, const SplitGeom &sg)
     return c[0] + sg.nc[0] * (c[1] + sg.nc[1] * c[2]);
 }
 
-// Particles per chaining cell (counts cleared by the caller).
+// Particles per chaining cell (counts cleared by the caller): a block counts
+// its kMlCountPer x kBlock particles per cell in an LDS hash table, then adds
+// each distinct cell's count with one global atomic.
+constexpr int kMlCountPer = 4;
 __global__ __launch_bounds__(kBlock) void k_ml_count(const int *__restrict__ cell3, int n,
                                                      SplitGeom sg, int *__restrict__ counts)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n)
-        atomicAdd(counts + split_cell_index(cell3[i], sg), 1);
+    __shared__ int hkey[kHash];
+    __shared__ int hcnt[kHash];
+    for (int h = threadIdx.x; h < kHash; h += kBlock) {
+        hkey[h] = -1;
+        hcnt[h] = 0;
+    }
+    __syncthreads();
+    const int base = blockIdx.x * kBlock * kMlCountPer;
+#pragma unroll
+    for (int k = 0; k < kMlCountPer; ++k) {
+        const int i = base + k * kBlock + threadIdx.x;
+        if (i < n)
+            atomicAdd(&hcnt[lds_hash_slot(hkey, split_cell_index(cell3[i], sg))], 1);
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < kHash; h += kBlock)
+        if (hcnt[h] > 0)
+            atomicAdd(counts + hkey[h], hcnt[h]);
 }
 
 // Kicks per subcycle: l = floor(rho / rho_0) / d + 1 clamped to [lmin, lmax],
@@ -238,13 +256,17 @@ __device__ __forceinline__ bool ml_kicks(int l, int m, int M)
     return t % M == 0 && ((t / M) & 1);
 }
 
+// Particles that kick after piece m: 1, or 2 above the lowest level.  The
+// short-range pass cuts the cells holding a 2 into finer work items: such a
+// pass runs over few, dense cells, and one wavefront per large chunk would
+// leave most of the GPU idle.
 __global__ __launch_bounds__(kBlock) void k_ml_active(const unsigned char *__restrict__ level,
-                                                      int n, int m, int M,
+                                                      int n, int m, int M, int lmin,
                                                       unsigned char *__restrict__ active)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n)
-        active[i] = ml_kicks(level[i], m, M) ? 1 : 0;
+        active[i] = ml_kicks(level[i], m, M) ? (level[i] > lmin ? 2 : 1) : 0;
 }
 
 // After stream piece m: particles of a level that kicks at m take v += a tau/l
@@ -260,7 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_ml_update(SplitGeom sg, int n, int *
                                                       const float *__restrict__ ay,
                                                       const float *__restrict__ az,
                                                       const unsigned char *__restrict__ level,
-                                                      int m, int M, double tau, double stream)
+                                                      int m, int M, double tau, double stream,
+                                                      int nstream)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
@@ -283,9 +306,13 @@ __global__ __launch_bounds__(kBlock) void k_ml_update(SplitGeom sg, int n, int *
     float *o[3] = {ox, oy, oz};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double off = (double)o[k][i] + (double)v[k] * stream;
-        rehome(off, c[k], sg.h[k], sg.nc[k]);
-        o[k][i] = (float)off;
+        float of = o[k][i];
+        for (int s = 0; s < nstream; ++s) {
+            double off = (double)of + (double)v[k] * stream;
+            rehome(off, c[k], sg.h[k], sg.nc[k]);
+            of = (float)off;
+        }
+        o[k][i] = of;
     }
     cell3[i] = pack3(c);
 }
@@ -452,32 +479,33 @@ int ml_levels_enqueue(sr_ctx *ctx, const SplitGeom &sg, const int *cell3, int n,
     if (rc)
         return rc;
     const dim3 grid((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_ml_count, grid, dim3(kBlock), 0, ctx->stream, cell3, n, sg, counts);
+    hipLaunchKernelGGL(k_ml_count, dim3((n + kBlock * kMlCountPer - 1) / (kBlock * kMlCountPer)),
+                       dim3(kBlock), 0, ctx->stream, cell3, n, sg, counts);
     hipLaunchKernelGGL(k_ml_level, grid, dim3(kBlock), 0, ctx->stream, cell3, n, sg, counts, d,
                        lmin, lmax, level);
     return sr_check_launch(ctx, "k_ml_level");
 }
 
-int ml_active_enqueue(sr_ctx *ctx, const unsigned char *level, int n, int m, int M,
+int ml_active_enqueue(sr_ctx *ctx, const unsigned char *level, int n, int m, int M, int lmin,
                       unsigned char *active)
 {
     if (n <= 0)
         return SR_OK;
     hipLaunchKernelGGL(k_ml_active, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, ctx->stream,
-                       level, n, m, M, active);
+                       level, n, m, M, lmin, active);
     return sr_check_launch(ctx, "k_ml_active");
 }
 
 int ml_update_enqueue(sr_ctx *ctx, const SplitGeom &sg, int n, int *cell3, float *ox, float *oy,
                       float *oz, float *vx, float *vy, float *vz, const float *ax,
                       const float *ay, const float *az, const unsigned char *level, int m, int M,
-                      double tau, double stream)
+                      double tau, double stream, int nstream)
 {
     if (n <= 0)
         return SR_OK;
     hipLaunchKernelGGL(k_ml_update, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, ctx->stream,
                        sg, n, cell3, ox, oy, oz, vx, vy, vz, ax, ay, az, level, m, M, tau,
-                       stream);
+                       stream, nstream);
     return sr_check_launch(ctx, "k_ml_update");
 }
 

@@ -91,24 +91,38 @@ extern "C" int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, fl
                                       lr_az, half_dt, 0.0)))
             return rc;
         const double piece = tau / M;
+        auto kicks_at = [&](int m) {
+            for (int l = p->ml_min; l <= p->ml_max; ++l)
+                if ((2 * m * l) % M == 0 && ((2 * m * l / M) & 1))
+                    return true;
+            return false;
+        };
+        // pieces streamed after piece m up to the next kick time (or the end
+        // of the subcycle), in one launch: nothing kicks in between
+        auto streams_after = [&](int m) {
+            int k = 0;
+            for (int q = m; q < M && (q == m || !kicks_at(q)); ++q)
+                ++k;
+            return k;
+        };
         for (int c = 0; c < p->n_sub; ++c) {
             if ((rc = ml_levels_enqueue(ctx, sg, cell3, ni, counts, p->ml_d, p->ml_min, p->ml_max,
                                         level)) ||
                 (rc = ml_update_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, nullptr,
-                                        nullptr, nullptr, level, 0, M, tau, piece)))
+                                        nullptr, nullptr, level, 0, M, tau, piece,
+                                        streams_after(0))))
                 return rc;
             for (int m = 1; m <= M; ++m) {
-                bool any = false;
-                for (int l = p->ml_min; l <= p->ml_max; ++l)
-                    any = any || ((2 * m * l) % M == 0 && ((2 * m * l / M) & 1));
-                if (any && ((rc = ml_active_enqueue(ctx, level, ni, m, M, active)) ||
-                            (rc = force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box,
-                                                     p->cell, p->r_max, p->eps, p->poly, sr_ax,
-                                                     sr_ay, sr_az, nullptr, active, nullptr))))
-                    return rc;
-                if ((rc = ml_update_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz,
-                                            any ? sr_ax : nullptr, sr_ay, sr_az, level, m, M, tau,
-                                            m < M ? piece : 0.0)))
+                if (!kicks_at(m))
+                    continue;  // its stream piece went with the last kick's launch
+                const int ns = streams_after(m);
+                if ((rc = ml_active_enqueue(ctx, level, ni, m, M, p->ml_min, active)) ||
+                    (rc = force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box, p->cell,
+                                             p->r_max, p->eps, p->poly, sr_ax, sr_ay, sr_az,
+                                             nullptr, active, nullptr)) ||
+                    (rc = ml_update_enqueue(ctx, sg, ni, cell3, ox, oy, oz, vx, vy, vz, sr_ax,
+                                            sr_ay, sr_az, level, m, M, tau, ns ? piece : 0.0,
+                                            ns)))
                     return rc;
             }
         }

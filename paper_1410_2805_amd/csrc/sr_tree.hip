@@ -381,7 +381,7 @@ __global__ __launch_bounds__(64) void k_leaf_boxes(int n, const int *__restrict_
             leaf_hi[l] = make_float4(hi[0], hi[1], hi[2], 0.f);
             // chunks of at most 64 targets: larger chunks at two targets per
             // lane measured slower here (fewer, longer items)
-            chunks[l] = chunks_for(e - a);
+            chunks[l] = tree_chunks(e - a);
         }
     }
 }

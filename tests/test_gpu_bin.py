@@ -44,7 +44,7 @@ def test_uniform_32k(sr, ctx):
     _assert_same(*_bin_both(sr, ctx, p.x, p.y, p.z, 32.0, 3.0))
 
 
-@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 1000, 1024, 1025, 3000, 40896, 40897, 70000])
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 129, 500, 1000, 1024, 1025, 3000, 40896, 40897, 70000])
 def test_one_cell_sizes(sr, ctx, n):
     """Every particle in one cell: exercises the register, LDS and
     multi-run merge paths of the per-cell sort (a whole-block sort in LDS up
