@@ -17,7 +17,8 @@ Prints ONE JSON line on stdout (progress goes to stderr):
             of the same box, on this host's cores
   accuracy  the timed result against the oracle on those targets
   config    also carries the 128^3 Zel'dovich box (the same measurement),
-            the batched form (64 boxes) and the serving form (Poisson trace)
+            the batched form (64 boxes), the serving form (Poisson trace) and
+            the multilevel full step against plain subcycles
 """
 from __future__ import annotations
 
@@ -324,7 +325,8 @@ def main():
     if args.workload == "ksk128":
         return bench_step(args)
     if args.workload == "ksk_ml128":
-        return bench_step_ml(args)
+        print(json.dumps(bench_step_ml(args)), flush=True)
+        return
     if args.workload == "tree":
         return bench_tree(args)
     if args.calib_copy:
@@ -371,9 +373,17 @@ def main():
                     "throughput_ratio_vs_fifo": s["throughput_ratio_vs_fifo"],
                     "saturation": s["saturation"], "accuracy": s["accuracy"]}
 
+        def multilevel():
+            m = bench_step_ml(args)["config"]
+            return {k: m[k] for k in ("workload", "zeldovich_plain_ms", "zeldovich_multilevel_ms",
+                                      "zeldovich_speedup", "zeldovich_particles_per_level",
+                                      "halo_box", "halo_plain_ms", "halo_multilevel_ms",
+                                      "halo_speedup", "halo_particles_per_level")}
+
         res["config"]["zeldovich128"] = _nested(zel, "zeldovich128")
         res["config"]["batched"] = _nested(batched, "batched")
         res["config"]["serving"] = _nested(serving, "serving")
+        res["config"]["multilevel"] = _nested(multilevel, "multilevel")
     print(json.dumps(res), flush=True)
 
 
@@ -726,9 +736,9 @@ def bench_step_ml(args):
         "roofline": None,
         "cpu_baseline": None,
     }
-    print(json.dumps(res), flush=True)
     pm.close()
     ctx.close()
+    return res
 
 
 def bench_tree(args):

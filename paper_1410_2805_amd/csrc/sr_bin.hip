@@ -151,27 +151,29 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
 {
     __shared__ int hkey[kHash];
     __shared__ int hcnt[kHash];
+    __shared__ int hflag[kMasked ? kHash : 1];
     for (int h = threadIdx.x; h < kHash; h += kBlock) {
         hkey[h] = -1;
         hcnt[h] = 0;
+        if (kMasked)
+            hflag[h] = 0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    int hs[kCellidPer], rk[kCellidPer];
+    int hs[kCellidPer], rk[kCellidPer], act[kCellidPer];
     const int base = blockIdx.x * kCellidBlock;
 #pragma unroll
     for (int k = 0; k < kCellidPer; ++k) {
         const int i = base + k * kBlock + threadIdx.x;
         const bool valid = i < B.ntot;
         int id = -1;
+        act[k] = 0;
         if (valid) {
             id = particle_cell(B, i, status);
             cid[i] = id;
             if (kMasked) {
                 const BoxDesc &d = box_at(B, find_box(B.pstart, B.nb, i));
-                const int v = d.active ? d.active[i - d.pbase] : 1;
-                if (v && flag[id] < v)  // the read only saves atomics; the maximum decides
-                    atomicMax(&flag[id], v);
+                act[k] = d.active ? d.active[i - d.pbase] : 1;
             }
         }
         hs[k] = -1;
@@ -203,12 +205,17 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
             hs[k] = h;
             rk[k] = atomicAdd(&hcnt[h], 1);
         }
+        if (kMasked && act[k] > 0)
+            atomicMax(&hflag[hs[k]], act[k]);
     }
     __syncthreads();
     for (int h = threadIdx.x; h < kHash; h += kBlock) {
         const int c = hcnt[h];
-        if (c > 0)
+        if (c > 0) {
+            if (kMasked && hflag[h] > 0)
+                atomicMax(&flag[hkey[h]], hflag[h]);
             hcnt[h] = atomicAdd(&count[hkey[h]], c);  // becomes the block's base
+        }
     }
     __syncthreads();
 #pragma unroll
