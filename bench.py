@@ -648,7 +648,7 @@ def bench_step_ml(args):
     poly = gridfit.poly_coeffs()
     box = sr.Box.make(L)
     n = 128 ** 3
-    ctx = sr.Context(0, arena_bytes=sr.sr_scratch_bytes(box, cell, n, True) + 3 * n + 2 ** 22)
+    ctx = sr.Context(0, arena_bytes=sr.sr_scratch_bytes(box, cell, n, 2))
     if args.xsplit:
         ctx.set_tuning(xsplit=args.xsplit)
     pm = sr.PM(ctx, ng, L)

@@ -110,8 +110,10 @@ int sr_sync(sr_ctx *ctx);
 int sr_grid_dims(const sr_box *box, double cell, int32_t dims[3], int64_t *n_cells);
 
 /* Scratch bytes sr_force (with_force = 1) or sr_bin (0) needs for n
- * particles in this geometry; a fixed arena of at least this size never
- * returns SR_ENOMEM for such a call. */
+ * particles in this geometry; with_force = 2: an sr_ksk_step with multilevel
+ * subcycles (its short-range passes with an activity mask, sub-item sums,
+ * levels and counts).  A fixed arena of at least this size never returns
+ * SR_ENOMEM for such a call. */
 int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force, size_t *bytes);
 
 /* Chaining-mesh binning (a stable counting sort by cell).
@@ -393,7 +395,7 @@ typedef struct sr_request {
 
 typedef struct sr_server_config {
     size_t hbm_budget;     /* bytes: half for resident state, half for pass scratch */
-    int32_t max_slots;     /* requests active at once (>= 1) */
+    int32_t max_slots;     /* requests active at once (1 .. 131072) */
     float r_max, eps;
     float poly[6];
     double cell;           /* chaining cell of every request's box */

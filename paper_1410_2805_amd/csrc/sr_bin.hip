@@ -516,11 +516,12 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
         const int len = offsets[c + 1] - offsets[c];
         int q = mesh_chunks(len);
         // an activity mask drops the cells without an active particle and
-        // cuts those flagged 2 into items of at most kFineChunk targets
-        // (k_cellid left the flags in chunk_count)
+        // cuts those flagged 2 into items of at most kFineChunk targets,
+        // marked kFineFlag for sub-items (k_cellid left the flags in
+        // chunk_count)
         if (q && box_at(B, find_box(B.cstart, B.nb, c)).active) {
             const int f = chunk_count[c];
-            q = f == 0 ? 0 : (f >= 2 ? (len + kFineChunk - 1) / kFineChunk : q);
+            q = f == 0 ? 0 : (f >= 2 ? ((len + kFineChunk - 1) / kFineChunk) | kFineFlag : q);
         }
         chunk_count[c] = q;
     }

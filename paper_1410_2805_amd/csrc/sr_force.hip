@@ -42,7 +42,7 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
                                              const int *__restrict__ perm,
                                              const int *__restrict__ mass_mixed,
                                              const ForceParams &fp, float4 *tile, Stencil &st,
-                                             int lane)
+                                             int lane, float4 *__restrict__ subsums)
 {
     const int kb = item.y, nt = item.z, S = item_split(item), box = item_box(item);
     const BoxDesc &d = box_at(B, box);
@@ -73,7 +73,10 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
     float acx = 0.f, acy = 0.f, acz = 0.f;
     float bcx = 0.f, bcy = 0.f, bcz = 0.f;
     if (__any((has_target && !pas) || (has2 && !pas2))) {
-        const int total = st.pbeg[kMaxPieces];
+        // a sub-item takes its part [sk T / ns, (sk + 1) T / ns) of the T sources
+        const int ns = item_nsub(item), sk = item_sub(item);
+        const int all = st.pbeg[kMaxPieces];
+        const int total = ns > 1 ? (int)((long long)(sk + 1) * all / ns) : all;
         // a pass stages `cap` sources (a multiple of the 4 S slice quantum, so
         // that padding stays inside the tile); the next pass's sources are
         // loaded before the current pass computes (each load waits for its
@@ -87,8 +90,8 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
         const TargetBox tb = target_box(xi, yi, zi, xj, yj, zj);
         float4 pre[kTile / 64];
         int p = 0;
-        int g0 = 0;
-        int cnt = total < cap ? total : cap;
+        int g0 = ns > 1 ? (int)((long long)sk * all / ns) : 0;
+        int cnt = total - g0 < cap ? total - g0 : cap;
         load_tile(pre, st, sorted, g0, cnt, lane, p);
         for (;;) {
             // kept sources, rounded up to the quantum with entries that add zero
@@ -146,10 +149,16 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
             acy += o.y;
             acz += o.z;
         }
-        const int orig = perm[kb + t] - d.pbase;
-        d.ax[orig] = pas ? 0.f : acx;
-        d.ay[orig] = pas ? 0.f : acy;
-        d.az[orig] = pas ? 0.f : acz;
+        const int nsub = item_nsub(item);
+        float4 *pp = nsub > 1 ? subsums + (size_t)item_sub(item) * B.ntot : nullptr;
+        if (pp) {
+            pp[kb + t] = pas ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(acx, acy, acz, 0.f);
+        } else {
+            const int orig = perm[kb + t] - d.pbase;
+            d.ax[orig] = pas ? 0.f : acx;
+            d.ay[orig] = pas ? 0.f : acy;
+            d.az[orig] = pas ? 0.f : acz;
+        }
         if (has2) {
             for (int q = 1; q < S; ++q) {
                 const float4 o = tile[64 + t + q * ln];
@@ -157,10 +166,15 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
                 bcy += o.y;
                 bcz += o.z;
             }
-            const int orig2 = perm[kb + t + ln] - d.pbase;
-            d.ax[orig2] = pas2 ? 0.f : bcx;
-            d.ay[orig2] = pas2 ? 0.f : bcy;
-            d.az[orig2] = pas2 ? 0.f : bcz;
+            if (pp) {
+                pp[kb + t + ln] =
+                    pas2 ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(bcx, bcy, bcz, 0.f);
+            } else {
+                const int orig2 = perm[kb + t + ln] - d.pbase;
+                d.ax[orig2] = pas2 ? 0.f : bcx;
+                d.ay[orig2] = pas2 ? 0.f : bcy;
+                d.az[orig2] = pas2 ? 0.f : bcz;
+            }
         }
     }
     __syncthreads();  // the tile is reused by the next item
@@ -177,19 +191,55 @@ __device__ __forceinline__ int item_position(int b)
     return ((j >> 6) * 8 + xcd) * 64 + (j & 63);
 }
 
+// One workgroup per item: the grid covers the item bound (a multiple of 512),
+// or, for passes with sub-items, at most kMaskedGrid workgroups that also
+// serve positions + k gridDim.
 __global__ __launch_bounds__(64) void k_force(Batch B, const int4 *__restrict__ items,
                                               const int *__restrict__ n_items,
                                               const float4 *__restrict__ sorted,
                                               const int *__restrict__ offsets,
                                               const int *__restrict__ perm,
-                                              const int *__restrict__ mass_mixed, ForceParams fp)
+                                              const int *__restrict__ mass_mixed, ForceParams fp,
+                                              float4 *__restrict__ subsums)
 {
     __shared__ float4 tile[kTile];
     __shared__ Stencil st;
-    const int pos = item_position(blockIdx.x);
-    if (pos >= *n_items)
-        return;
-    process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st, threadIdx.x);
+    const int n = *n_items;
+    for (int pos = item_position(blockIdx.x); pos < n; pos += gridDim.x)
+        process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st, threadIdx.x,
+                     subsums);
+}
+
+// Adds the partial sums of the sub-items of every chunk, in sub-item order,
+// and writes the chunk's accelerations (the first sub-item's workgroup;
+// passive targets' partials are exact zeros).
+__global__ __launch_bounds__(64) void k_subsum(Batch B, const int4 *__restrict__ items,
+                                               const int *__restrict__ n_items,
+                                               const int *__restrict__ perm,
+                                               const float4 *__restrict__ subsums)
+{
+    const int n = *n_items;
+    for (int pos = blockIdx.x; pos < n; pos += gridDim.x) {
+        const int4 item = items[pos];
+        const int ns = item_nsub(item);
+        if (ns == 1 || item_sub(item) != 0)
+            continue;
+        const BoxDesc &d = box_at(B, item_box(item));
+        for (int t = threadIdx.x; t < item.z; t += 64) {
+            const int slot = item.y + t;
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            for (int k = 0; k < ns; ++k) {
+                const float4 v = subsums[(size_t)k * B.ntot + slot];
+                ax += v.x;
+                ay += v.y;
+                az += v.z;
+            }
+            const int orig = perm[slot] - d.pbase;
+            d.ax[orig] = ax;
+            d.ay[orig] = ay;
+            d.az[orig] = az;
+        }
+    }
 }
 
 // Persistent variant: a fixed grid of workgroups takes items in order from a
@@ -215,7 +265,7 @@ __global__ __launch_bounds__(64) void k_force_persistent(Batch B, const int4 *__
         if (pos >= n)
             break;
         process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st,
-                     threadIdx.x);
+                     threadIdx.x, nullptr);
     }
 }
 
@@ -302,10 +352,14 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
     }
 }
 
-// One thread per cell: its chunk_count[c] work items (cell_items), written at
-// a range the block reserves with one atomic on *n_items.  The order of the
-// items then depends on which block reserves first; no result does, since
-// every target is summed inside one item in a fixed order.
+// Work items of a block of 256 cells: each thread takes one cell's chunk
+// count and stencil size (sub-items for cells flagged kFineFlag), the block
+// reserves its item range with one atomic on *n_items, then all threads
+// write the block's items, thread j the items j, j + 256, ... (the cell of an
+// item found by a binary search over the block's running item counts).  The
+// order of the items depends on which block reserves first; no result does:
+// every target is summed in a fixed order, by one item or by its chunk's
+// sub-items added in order.
 __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ offsets,
                                                const int *__restrict__ chunk_count,
                                                int4 *__restrict__ items,
@@ -314,11 +368,25 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
 {
     __shared__ int wsum[4];
     __shared__ int base;
+    __shared__ int s_end[256];  // the block's items up to and including each cell
+    __shared__ int s_q[256], s_ns[256], s_b[256], s_len[256], s_box[256];
+    __shared__ long long s_src[256];
     const int c = blockIdx.x * 256 + threadIdx.x;
-    const int q = c < B.ctot ? chunk_count[c] : 0;
+    const int cc = c < B.ctot ? chunk_count[c] : 0;
+    const int q = cc & (kFineFlag - 1);
+    int ns = 1, box = 0, b = 0, len = 0;
+    long long src = 0;
+    if (q > 0) {
+        src = cell_stencil(B, offsets, c, &box, &b, &len);
+        if (cc & kFineFlag) {
+            const long long k = (src + kSplitSources - 1) / kSplitSources;
+            ns = k < 1 ? 1 : (k > kMaxSrcSplit ? kMaxSrcSplit : (int)k);
+        }
+    }
+    const int m = q * ns;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int tot;
-    const int ex = wave_exclusive_scan(q, lane, &tot);
+    int first = wave_exclusive_scan(m, lane, &tot);
     if (lane == 0)
         wsum[wid] = tot;
     __syncthreads();
@@ -326,12 +394,33 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
         const int t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
         base = t > 0 ? atomicAdd(n_items, t) : 0;
     }
+    for (int j = 0; j < wid; ++j)
+        first += wsum[j];
+    s_end[threadIdx.x] = first + m;
+    s_q[threadIdx.x] = q;
+    s_ns[threadIdx.x] = ns;
+    s_b[threadIdx.x] = b;
+    s_len[threadIdx.x] = len;
+    s_box[threadIdx.x] = box;
+    s_src[threadIdx.x] = src;
     __syncthreads();
-    if (q > 0) {
-        int first = base + ex;
-        for (int j = 0; j < wid; ++j)
-            first += wsum[j];
-        cell_items(B, offsets, c, q, first, items, item_cost);
+    const int T = s_end[255];
+    for (int j = threadIdx.x; j < T; j += 256) {
+        int lo = 0, hi = 255;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_end[mid] > j)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        const int qq = s_q[lo], nn = s_ns[lo];
+        const int r = j - (s_end[lo] - qq * nn);
+        const int k = r / nn;
+        int bucket;
+        items[base + j] = cell_item(blockIdx.x * 256 + lo, s_box[lo], s_b[lo], s_len[lo], qq, k,
+                                    nn, r - k * nn, s_src[lo], &bucket);
+        item_cost[base + j] = bucket;
     }
 }
 
@@ -482,6 +571,8 @@ __global__ __launch_bounds__(256) void k_momentum_final(const double *__restrict
         out[3 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+constexpr unsigned kMaskedGrid = 65536;  // workgroups of a masked pass at most (a multiple of 512)
+
 unsigned grid_for_items(int64_t ub)
 {
     return (unsigned)((ub + 511) & ~int64_t(511));
@@ -494,16 +585,20 @@ int lpt_blocks(int64_t ub)
 
 }  // namespace
 
-int64_t item_bound(int64_t ntot, int64_t ctot)
+int64_t item_bound(int64_t ntot, int64_t ctot, bool masked)
 {
     int64_t nonempty = ntot < ctot ? ntot : ctot;
-    return nonempty + ntot / 16 + 1;  // see chunks_for
+    // plain: at most max(ceil(n / 64), n / 16) chunks per cell (chunks_for);
+    // masked: flagged cells take ceil(n / kFineChunk) <= n / 32 + 1 chunks of
+    // at most kMaxSrcSplit sub-items each, and kMaxSrcSplit (n / 32 + 1) also
+    // bounds the plain count
+    return masked ? kMaxSrcSplit * (nonempty + ntot / 32 + 1) : nonempty + ntot / 16 + 1;
 }
 
-void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s)
+void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s, bool masked)
 {
     size_t nn = (size_t)(ntot > 0 ? ntot : 1);
-    const int64_t ub = item_bound(ntot, ctot);
+    const int64_t ub = item_bound(ntot, ctot, masked);
     bin_layout(b, ntot, ctot, nb, s.bin);
     s.offsets = b.take<int>((size_t)ctot + 1);
     s.perm = b.take<int>(nn);
@@ -514,6 +609,7 @@ void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s)
     s.items_lpt = b.take<int4>((size_t)ub);
     s.queue = b.take<int>(1);
     s.mom_part = b.take<double>((size_t)(nb > 0 ? nb : 1) * kRedBlocks * 3);
+    s.part = masked ? b.take<float4>(nn * kMaxSrcSplit) : nullptr;
 }
 
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly)
@@ -601,7 +697,8 @@ static int bin_items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s,
         return rc;
     if (order == 1)
         return lpt_sort_enqueue(ctx, s.items, s.item_cost, s.bin.n_items,
-                                item_bound(B.ntot, B.ctot), s.bin.lpt, s.items_lpt);
+                                item_bound(B.ntot, B.ctot, s.part != nullptr), s.bin.lpt,
+                                s.items_lpt);
     return SR_OK;
 }
 
@@ -616,7 +713,9 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
     const int4 *items = order == 1 ? s.items_lpt : s.items;
     const int *n_items = s.bin.n_items;
     if (B.ntot > 0) {
-        if (persistent) {
+        // passes with sub-items need k_subsum after the pair loop: they take the
+        // grid below whatever the persistence setting
+        if (persistent && !s.part) {
             int dev_cus = 256;
             (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount,
                                         ctx->device);
@@ -630,9 +729,19 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
                                B, items, n_items, s.sorted, s.offsets, s.perm, s.bin.mass_mixed,
                                fp, s.queue);
         } else {
-            hipLaunchKernelGGL(k_force, dim3(grid_for_items(item_bound(B.ntot, B.ctot))),
-                               dim3(64), 0, ctx->stream, B, items, n_items, s.sorted, s.offsets,
-                               s.perm, s.bin.mass_mixed, fp);
+            // a pass with sub-items (masked) has a loose item bound: a capped
+            // grid walks it
+            unsigned grid = grid_for_items(item_bound(B.ntot, B.ctot, s.part != nullptr));
+            if (s.part && grid > kMaskedGrid)
+                grid = kMaskedGrid;
+            hipLaunchKernelGGL(k_force, dim3(grid), dim3(64), 0, ctx->stream, B, items, n_items,
+                               s.sorted, s.offsets, s.perm, s.bin.mass_mixed, fp, s.part);
+            if (s.part) {
+                if ((rc = sr_check_launch(ctx, "k_force")))
+                    return rc;
+                hipLaunchKernelGGL(k_subsum, dim3(grid), dim3(64), 0, ctx->stream, B, items,
+                                   n_items, s.perm, s.part);
+            }
         }
         if ((rc = sr_check_launch(ctx, "k_force")))
             return rc;
@@ -714,7 +823,8 @@ int force_split_masked(sr_ctx *ctx, const int32_t *cell3, const float *ox, const
     B.one.active = active;
     Bump sz{nullptr, 0, 0};
     ForceScratch s;
-    force_layout(sz, n, B.ctot, 1, s);
+    const bool masked = active != nullptr;
+    force_layout(sz, n, B.ctot, 1, s, masked);
     if (bytes) {
         *bytes = sz.off;
         return SR_OK;
@@ -724,7 +834,7 @@ int force_split_masked(sr_ctx *ctx, const int32_t *cell3, const float *ox, const
     if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
-    force_layout(b, n, B.ctot, 1, s);
+    force_layout(b, n, B.ctot, 1, s, masked);
     const ForceParams fp = make_params(r_max, eps, poly);
     const int rec = sr_timing_begin(ctx);
     return force_enqueue(ctx, B, s, fp, ctx->order, ctx->persistent, momentum3, rec);
@@ -745,7 +855,7 @@ extern "C" int sr_force_split(sr_ctx *ctx, const int32_t *cell3, const float *ox
 extern "C" int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force,
                                 size_t *bytes)
 {
-    if (!bytes || n < 0 || n > INT_MAX)
+    if (!bytes || n < 0 || n > INT_MAX || with_force < 0 || with_force > 2)
         return SR_EINVAL;
     Geom g;
     // with_force: the largest x split any context may use
@@ -754,7 +864,17 @@ extern "C" int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int w
     Bump sz{nullptr, 0, 0};
     if (with_force) {
         ForceScratch s;
-        force_layout(sz, n, g.ncell, 1, s);
+        force_layout(sz, n, g.ncell, 1, s, with_force == 2);
+        if (with_force == 2) {
+            // the multilevel step's levels, activity mask and cell counts
+            // (sr_ksk_step lays them out after the force pass)
+            Geom g1;
+            if (sr_make_geom(nullptr, box, cell, &g1, 1))
+                return SR_EINVAL;
+            sz.take<unsigned char>((size_t)n);
+            sz.take<unsigned char>((size_t)n);
+            sz.take<int>((size_t)g1.ncell);
+        }
     } else {
         BinScratch s;
         bin_layout(sz, n, g.ncell, 1, s);

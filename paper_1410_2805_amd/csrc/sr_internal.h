@@ -202,6 +202,7 @@ struct ForceScratch {
     int4 *items_lpt;  // [item bound] items by decreasing cost bucket
     int *queue;       // [1] persistent work counter
     double *mom_part; // [nb * kRedBlocks * 3]
+    float4 *part;     // [kMaxSrcSplit * ntot] sub-item partial sums (masked passes), or null
 };
 
 constexpr int kRedBlocks = 512;    // FP64 reduction blocks per box (at most)
@@ -234,8 +235,11 @@ int fill_enqueue(sr_ctx *ctx, int *p, int value, int64_t count);
 int clear_enqueue(sr_ctx *ctx, const ClearList &cl);
 
 // Force pass (sr_force.hip)
-int64_t item_bound(int64_t ntot, int64_t ctot);
-void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s);
+// Items of a pass at most; masked: a pass with an activity mask, whose
+// flagged cells may take finer items and sub-items.
+int64_t item_bound(int64_t ntot, int64_t ctot, bool masked = false);
+void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s,
+                  bool masked = false);
 int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int xsplit,
                    Geom *g);
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly);
@@ -382,14 +386,28 @@ __device__ __forceinline__ int mesh_chunks(int n)
     return n <= 4 * kChunk ? (n > 0 ? kChunkTab.mesh[n] : 0) : (n + kChunk2 - 1) / kChunk2;
 }
 
-// Work items of cell c (global id), q of them, written at items[first ..
-// first + q): the cell's targets cut into q nearly equal chunks [k n / q,
-// (k + 1) n / q), each shaped by item_shape, as {c, first sorted slot,
-// targets, S | (tpl - 1) << 5 | box << 6}.  Each item also gets the cost
-// bucket floor(log2(cost)), cost = (sources of the cell's stencil) x (the
-// shape's cost per source) + 64 (wavefront iterations plus overhead).
-__device__ inline void cell_items(const Batch &B, const int *__restrict__ offsets, int c, int q,
-                                  int first, int4 *__restrict__ items, int *__restrict__ item_cost)
+// Work items.  A cell of n targets is cut into q nearly equal chunks [k n /
+// q, (k + 1) n / q); a chunk is one item, or, in cells flagged for finer
+// items (multilevel passes over few dense cells), ns sub-items that take
+// consecutive parts [sk T / ns, (sk + 1) T / ns) of the T stencil sources,
+// so that one dense cell's pairs spread over more wavefronts.  A sub-item
+// leaves partial sums, which a second pass adds in sub-item order.
+constexpr int kMaxSrcSplit = 8;       // sub-items per chunk at most
+constexpr int kSplitSources = 4096;   // stencil sources per sub-item, about
+constexpr int kFineFlag = 1 << 30;    // chunk_count bit: cell flagged for finer items
+constexpr int kMaxBatchBoxes = 1 << 17;
+
+// Item layout: {cell (global), first sorted slot, targets, S | (tpl - 1) << 5
+// | sk << 6 | (ns - 1) << 10 | box << 14}.
+__host__ __device__ inline int item_word(int S, int tpl, int sk, int ns, int box)
+{
+    return S | (tpl - 1) << 5 | sk << 6 | (ns - 1) << 10 | box << 14;
+}
+
+// Stencil size of cell c (global id): the sources of its 9 x-rows of 2 hx + 1
+// cells (shifts aside); also its box, first sorted slot and particle count.
+__device__ inline long long cell_stencil(const Batch &B, const int *__restrict__ offsets, int c,
+                                         int *box_out, int *b_out, int *len_out)
 {
     const int box = find_box(B.cstart, B.nb, c);
     const BoxDesc &d = box_at(B, box);
@@ -399,7 +417,6 @@ __device__ inline void cell_items(const Batch &B, const int *__restrict__ offset
     const int lc = c - d.cbase, plane = g.nc[0] * g.nc[1];
     const int cz = lc / plane, cy = (lc - cz * plane) / g.nc[0];
     const int cx = lc - cz * plane - cy * g.nc[0];
-    // stencil size: the 9 x-rows of 2 hx + 1 cells (shifts aside)
     const int *off = offsets + d.cbase;
     long long src = 0;
 #pragma unroll
@@ -425,15 +442,26 @@ __device__ inline void cell_items(const Batch &B, const int *__restrict__ offset
             src += off[row + e + 1] - off[row + a];
         }
     }
+    *box_out = box;
+    *b_out = b;
+    *len_out = len;
+    return src;
+}
+
+// Sub-item sk of chunk k of a cell (first sorted slot b, len targets, q
+// chunks, ns sub-items per chunk, src stencil sources), shaped by item_shape;
+// *bucket is floor(log2(cost)), cost = (the sub-item's sources) x (the
+// shape's cost per source) + 64 (wavefront iterations plus overhead).
+__device__ inline int4 cell_item(int c, int box, int b, int len, int q, int k, int ns, int sk,
+                                 long long src, int *bucket)
+{
     // k len fits in 32 bits below 46341 targets (q <= len)
     const bool small = len <= 46340;
-    for (int k = 0; k < q; ++k) {
-        const int lo = small ? k * len / q : (int)((long long)k * len / q);
-        const int hi = small ? (k + 1) * len / q : (int)((long long)(k + 1) * len / q);
-        int tpl, S;
-        const float pass = item_shape(hi - lo, &tpl, &S);
-        items[first + k] = make_int4(c, b + lo, hi - lo, S | (tpl - 1) << 5 | box << 6);
-        const long long cost = (long long)((float)src * pass) + 64;
-        item_cost[first + k] = 63 - __clzll((unsigned long long)cost);
-    }
+    const int lo = small ? k * len / q : (int)((long long)k * len / q);
+    const int hi = small ? (k + 1) * len / q : (int)((long long)(k + 1) * len / q);
+    int tpl, S;
+    const float pass = item_shape(hi - lo, &tpl, &S);
+    const long long cost = (long long)((float)(src / ns) * pass) + 64;
+    *bucket = 63 - __clzll((unsigned long long)cost);
+    return make_int4(c, b + lo, hi - lo, item_word(S, tpl, sk, ns, box));
 }

@@ -375,10 +375,13 @@ __device__ __forceinline__ void pair_tile2(const float4 *src, int cnt, float xi,
     }
 }
 
-// Item layout: {cell (global), first sorted slot, targets, S | two << 5 |
-// box << 6}, two = 1 when each lane holds two targets.
+// Item layout (item_word): {cell (global), first sorted slot, targets, S |
+// two << 5 | sk << 6 | (ns - 1) << 10 | box << 14}, two = 1 when each lane
+// holds two targets, sk of ns the sub-item's part of the stencil sources.
 __device__ __forceinline__ int item_split(const int4 &it) { return it.w & 31; }
 __device__ __forceinline__ bool item_two(const int4 &it) { return (it.w >> 5) & 1; }
-__device__ __forceinline__ int item_box(const int4 &it) { return it.w >> 6; }
+__device__ __forceinline__ int item_sub(const int4 &it) { return (it.w >> 6) & 15; }
+__device__ __forceinline__ int item_nsub(const int4 &it) { return ((it.w >> 10) & 15) + 1; }
+__device__ __forceinline__ int item_box(const int4 &it) { return it.w >> 14; }
 
 }  // namespace

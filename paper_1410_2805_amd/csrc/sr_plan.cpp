@@ -179,6 +179,8 @@ extern "C" int sr_plan_create(sr_ctx *ctx, const sr_batch_box *boxes, int nboxes
     ctx->err.clear();
     if (nboxes < 1 || !boxes)
         return sr_fail(ctx, SR_EINVAL, "need at least one box");
+    if (nboxes > kMaxBatchBoxes)
+        return sr_fail(ctx, SR_EINVAL, "at most %d boxes per plan", kMaxBatchBoxes);
     int rc = check_force_params(ctx, r_max, eps, poly);
     if (rc)
         return rc;

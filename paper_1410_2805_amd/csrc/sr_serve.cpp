@@ -217,8 +217,11 @@ extern "C" int sr_server_create(sr_ctx *ctx, const sr_server_config *cfg, sr_ser
     int rc = check_force_params(ctx, cfg->r_max, cfg->eps, cfg->poly);
     if (rc)
         return rc;
-    if (cfg->max_slots < 1 || cfg->hbm_budget < (size_t)(64u << 20) || !(cfg->cell > 0.0))
-        return sr_fail(ctx, SR_EINVAL, "need max_slots >= 1, hbm_budget >= 64 MiB, cell > 0");
+    if (cfg->max_slots < 1 || cfg->max_slots > kMaxBatchBoxes ||
+        cfg->hbm_budget < (size_t)(64u << 20) || !(cfg->cell > 0.0))
+        return sr_fail(ctx, SR_EINVAL,
+                       "need 1 <= max_slots <= %d, hbm_budget >= 64 MiB, cell > 0",
+                       kMaxBatchBoxes);
     const sr_tuning &t = cfg->tuning;
     if (t.xsplit < 1 || t.xsplit > kMaxXsplit || t.order < 0 || t.order > 1 ||
         t.persistent < 0 || t.persistent > 1)

@@ -53,9 +53,12 @@ extern "C" int sr_ksk_step(sr_ctx *ctx, sr_pm *pm, int32_t *cell3, float *ox, fl
     unsigned char *level = nullptr, *active = nullptr;
     int *counts = nullptr;
     if (ml) {
+        // sized for a masked pass (finer items, sub-item sums); the sizing
+        // call only tests the mask pointer for null
+        static const unsigned char any_mask = 1;
         size_t fbytes = 0;
         if ((rc = force_split_masked(ctx, cell3, ox, oy, oz, mass, n, box, p->cell, p->r_max,
-                                     p->eps, p->poly, sr_ax, sr_ay, sr_az, nullptr, nullptr,
+                                     p->eps, p->poly, sr_ax, sr_ay, sr_az, nullptr, &any_mask,
                                      &fbytes)))
             return rc;
         const size_t a = 256;

@@ -218,10 +218,12 @@ def sr_grid_dims(box: Box, cell: float):
     return tuple(dims), int(nc.value)
 
 
-def sr_scratch_bytes(box: Box, cell: float, n: int, with_force: bool = True) -> int:
+def sr_scratch_bytes(box: Box, cell: float, n: int, with_force=True) -> int:
+    """with_force: True / 1 sr_force, False / 0 sr_bin, 2 a multilevel
+    sr_ksk_step."""
     out = ctypes.c_size_t()
-    rc = lib.sr_scratch_bytes(ctypes.byref(box), float(cell), int(n), int(bool(with_force)),
-                              ctypes.byref(out))
+    mode = 2 if with_force == 2 and not isinstance(with_force, bool) else int(bool(with_force))
+    rc = lib.sr_scratch_bytes(ctypes.byref(box), float(cell), int(n), mode, ctypes.byref(out))
     if rc:
         raise SRError(rc, "bad geometry")
     return int(out.value)

@@ -39,6 +39,10 @@ def test_grid_dims_and_scratch():
         sr.sr_grid_dims(sr.Box.make(10.0), 0.0)
     b1 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, True)
     b0 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, False)
+    # the multilevel step: masked passes (sub-item sums of 8 x 16 B per
+    # particle) plus its levels, mask and cell counts
+    b2 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, 2)
+    assert b2 > b1 + 8 * 16 * 2 ** 21
     assert b1 > b0 > 2 ** 21 * 8
     # box sides are bounded so that tile padding (at 1e6) stays beyond every cutoff
     assert sr.sr_scratch_bytes(sr.Box.make((131072.0, 12.0, 12.0)), 3.0, 1000, True) > 0

@@ -112,6 +112,38 @@ def test_multilevel_step_matches_oracle(sr, ctx, d, lmin, lmax):
     assert np.abs(dx).max() <= 2e-5 * dt * vs + 1e-6
 
 
+@pytest.mark.parametrize("n,seed", [(20000, 7), (60000, 8)])
+def test_multilevel_dense_cells_match_oracle(sr, ctx, n, seed):
+    """Dense cells whose stencils hold 4,096..19,329 sources: the multilevel
+    passes cut them into finer items whose stencil sources are split over up
+    to five sub-items, summed afterwards in order; the step still follows the
+    FP64 oracle."""
+    L, pos, vel, m = _clustered(n=n, seed=seed)
+    poly = gridfit.poly_coeffs()
+    dt = 0.02
+    pmh = sr.PM(ctx, 16, L)
+    try:
+        box, st = _state(sr, ctx, L, pos, vel, m)
+        gp, gv = _run(sr, ctx, pmh, box, st,
+                      sr.StepParams.make(R_MAX, EPS, poly, CELL, dt, 1, ml=(4, 1, 3)))
+        # the same step again from the same state: bitwise reproducible
+        box, st = _state(sr, ctx, L, pos, vel, m)
+        gp2, gv2 = _run(sr, ctx, pmh, box, st,
+                        sr.StepParams.make(R_MAX, EPS, poly, CELL, dt, 1, ml=(4, 1, 3)))
+    finally:
+        pmh.close()
+    assert np.array_equal(gp, gp2) and np.array_equal(gv, gv2)
+    P, V, _, _ = PMO.ksk_step(pos, vel.astype(np.float64), m.astype(np.float64), L, 16, R_MAX,
+                              EPS, poly.astype(np.float64), dt, 1, ml=(4, 1, 3, CELL))
+    dx = gp - P
+    dx -= L * np.round(dx / L)
+    vs = np.sqrt((V ** 2).sum(1).mean())
+    dv = np.abs(gv - V).max()
+    print("n=%d: max|dv| %.3e (rms v %.3e) max|dx| %.3e" % (n, dv, vs, np.abs(dx).max()))
+    assert dv <= 2e-5 * vs + 1e-5
+    assert np.abs(dx).max() <= 2e-5 * dt * vs + 1e-6
+
+
 def test_multilevel_parameters_rejected(sr, ctx):
     L, pos, vel, m = _clustered(n=500)
     pmh = sr.PM(ctx, 16, L)
