@@ -140,14 +140,18 @@ constexpr int kPeelGroup = 4;  // ... while the groups found hold at least this 
 // one ballot and served by a single pair of LDS atomics for the whole group,
 // repeated while such groups are large; the remaining lanes go one by one.
 //
-// With an activity mask (kMasked; flag cleared) the pass also leaves in
-// flag[cell] the largest activity value of the cell's particles (1, or 2 for
-// cells cut into finer work items; 0: no active particle).
+// With an activity mask (kMasked; flag and tcount cleared) the pass also
+// leaves in flag[cell] the largest activity value of the cell's particles (1,
+// or 2 for cells cut into finer work items; 0: no active particle) and in
+// tcount[cell] the number of its active particles.  A block keeps both in one
+// LDS word per cell: the active count in the low kActShift bits, the count of
+// those with value 2 above them (at most kCellidBlock each).
+constexpr int kActShift = 20;
 template <bool kMasked>
 __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ cid,
                                                    int *__restrict__ slot,
                                                    int *__restrict__ count, int *__restrict__ status,
-                                                   int *__restrict__ flag)
+                                                   int *__restrict__ flag, int *__restrict__ tcount)
 {
     __shared__ int hkey[kHash];
     __shared__ int hcnt[kHash];
@@ -179,6 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
         hs[k] = -1;
         rk[k] = 0;
         unsigned long long rem = __ballot(valid);
+        const unsigned long long act_b = kMasked ? __ballot(act[k] > 0) : 0ull;
+        const unsigned long long fine_b = kMasked ? __ballot(act[k] == 2) : 0ull;
         for (int it = 0; it < kPeelMax && rem; ++it) {
             const int leader = __ffsll((long long)rem) - 1;
             const int key = __builtin_amdgcn_readlane(id, leader);
@@ -188,6 +194,9 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
             if (lane == leader) {
                 hh = lds_hash_slot(hkey, key);
                 hb = atomicAdd(&hcnt[hh], gsize);
+                if (kMasked && (act_b & grp))
+                    atomicAdd(&hflag[hh], __popcll(act_b & grp) +
+                                              (__popcll(fine_b & grp) << kActShift));
             }
             hh = __builtin_amdgcn_readlane(hh, leader);
             hb = __builtin_amdgcn_readlane(hb, leader);
@@ -204,16 +213,18 @@ __global__ __launch_bounds__(kBlock) void k_cellid(Batch B, int *__restrict__ ci
             const int h = lds_hash_slot(hkey, id);
             hs[k] = h;
             rk[k] = atomicAdd(&hcnt[h], 1);
+            if (kMasked && act[k] > 0)
+                atomicAdd(&hflag[h], act[k] == 2 ? 1 + (1 << kActShift) : 1);
         }
-        if (kMasked && act[k] > 0)
-            atomicMax(&hflag[hs[k]], act[k]);
     }
     __syncthreads();
     for (int h = threadIdx.x; h < kHash; h += kBlock) {
         const int c = hcnt[h];
         if (c > 0) {
-            if (kMasked && hflag[h] > 0)
-                atomicMax(&flag[hkey[h]], hflag[h]);
+            if (kMasked && hflag[h] > 0) {
+                atomicMax(&flag[hkey[h]], (hflag[h] >> kActShift) > 0 ? 2 : 1);
+                atomicAdd(&tcount[hkey[h]], hflag[h] & ((1 << kActShift) - 1));
+            }
             hcnt[h] = atomicAdd(&count[hkey[h]], c);  // becomes the block's base
         }
     }
@@ -289,14 +300,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int *__restrict__ in
     }
 }
 
+// With an activity mask the slots of active particles take the sort key
+// i | INT_MIN, so that the cell sorts put them first (in index order), ahead
+// of the inactive ones; the sorts store the plain index (key & INT_MAX).
 __global__ __launch_bounds__(kBlock) void k_scatter(const int *__restrict__ cid,
                                                     const int *__restrict__ slot, int n,
                                                     const int *__restrict__ offsets,
+                                                    const unsigned char *__restrict__ active,
                                                     int *__restrict__ perm)
 {
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n)
-        perm[offsets[cid[i]] + slot[i]] = i;
+        perm[offsets[cid[i]] + slot[i]] = active && active[i] ? (i | INT_MIN) : i;
 }
 
 __device__ __forceinline__ int bitonic64(int v, int lane)
@@ -442,13 +457,14 @@ __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int 
         for (int k = 0; k < len; ++k)
             rank += __builtin_amdgcn_readlane(v, k) < v ? 1 : 0;
         if (lane < len) {
-            perm[b + rank] = v;
+            const int u = v & INT_MAX;
+            perm[b + rank] = u;
             if (inv)
-                inv[v] = b + rank;
+                inv[u] = b + rank;
         }
     } else if (len <= 64) {
         int v = lane < len ? perm[b + lane] : INT_MAX;
-        v = bitonic64(v, lane);
+        v = bitonic64(v, lane) & INT_MAX;
         if (lane < len) {
             perm[b + lane] = v;
             if (inv)
@@ -479,7 +495,7 @@ __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int 
             wave_sync();
         }
         for (int t = lane; t < len; t += 64) {
-            int v = sb[t];
+            const int v = sb[t] & INT_MAX;
             perm[b + t] = v;
             if (inv)
                 inv[v] = b + t;
@@ -497,12 +513,14 @@ __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int 
 // among the smaller indices of the same cell (one pass for the whole group);
 // otherwise the cells are sorted one after the other.  With chunk_count, the
 // pass also counts the force work items of each cell (mesh_chunks_for).
+// Indices are compared as the signed keys k_scatter wrote.
 __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restrict__ offsets,
                                                     int *__restrict__ perm,
                                                     int *__restrict__ large_list,
                                                     int *__restrict__ large_count,
                                                     int *__restrict__ inv,
-                                                    int *__restrict__ chunk_count)
+                                                    int *__restrict__ chunk_count,
+                                                    const int *__restrict__ tcount)
 {
     __shared__ int buf[kBlock / 64][kLargeCell];
     const int lane = threadIdx.x & 63;
@@ -515,13 +533,16 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
         const int c = c0 + lane;
         const int len = offsets[c + 1] - offsets[c];
         int q = mesh_chunks(len);
-        // an activity mask drops the cells without an active particle and
-        // cuts those flagged 2 into items of at most kFineChunk targets,
-        // marked kFineFlag for sub-items (k_cellid left the flags in
-        // chunk_count)
-        if (q && box_at(B, find_box(B.cstart, B.nb, c)).active) {
-            const int f = chunk_count[c];
-            q = f == 0 ? 0 : (f >= 2 ? ((len + kFineChunk - 1) / kFineChunk) | kFineFlag : q);
+        // with an activity mask only the cell's na active particles (sorted
+        // first) are targets: cells without one get no item, those flagged 2
+        // are cut into items of at most kFineChunk targets, marked kFineFlag
+        // for sub-items (k_cellid left the flags in chunk_count, the counts
+        // in tcount)
+        if (tcount) {
+            const int f = chunk_count[c], na = tcount[c];
+            q = f == 0 ? 0
+                       : (f >= 2 ? ((na + kFineChunk - 1) / kFineChunk) | kFineFlag
+                                 : mesh_chunks(na));
         }
         chunk_count[c] = q;
     }
@@ -556,9 +577,10 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
             rank += (j < len && u < v) ? 1 : 0;
         }
         if (lane < total) {
-            perm[cb + rank] = v;
+            const int iv = v & INT_MAX;
+            perm[cb + rank] = iv;
             if (inv)
-                inv[v] = cb + rank;
+                inv[iv] = cb + rank;
         }
         return;
     }
@@ -668,7 +690,7 @@ __global__ __launch_bounds__(kLargeBlock) void k_segsort_large(Batch B,
                 buf[e] = perm[b + e];
             const int *sorted_idx = lds_sort_cell(buf, len, tmp + b);
             for (int e = threadIdx.x; e < len; e += kLargeBlock) {
-                const int v = sorted_idx[e];
+                const int v = sorted_idx[e] & INT_MAX;
                 perm[b + e] = v;
                 if (inv)
                     inv[v] = b + e;
@@ -760,14 +782,13 @@ __global__ __launch_bounds__(kLargeBlock) void k_segsort_large(Batch B,
             src = dst;
             dst = t;
         }
-        if (src != perm + b) {
-            for (int e = threadIdx.x; e < len; e += kLargeBlock)
-                perm[b + e] = src[e];
-            __syncthreads();
-        }
-        if (inv) {
-            for (int e = threadIdx.x; e < len; e += kLargeBlock)
-                inv[perm[b + e]] = b + e;
+        // the plain indices, in perm (in place when the last round wrote perm:
+        // every thread rewrites only its own entries)
+        for (int e = threadIdx.x; e < len; e += kLargeBlock) {
+            const int v = src[e] & INT_MAX;
+            perm[b + e] = v;
+            if (inv)
+                inv[v] = b + e;
         }
         __syncthreads();
     }
@@ -846,9 +867,10 @@ void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
 }
 
 // Enqueue the whole binning pass.  sorted and chunk_count may be NULL (then
-// no gather and no item counts).
+// no gather and no item counts); tcount (per-cell active counts) is given
+// exactly when the pass carries an activity mask.
 int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, int *perm,
-                float4 *sorted, int *chunk_count)
+                float4 *sorted, int *chunk_count, int *tcount)
 {
     int rc;
     {
@@ -870,18 +892,23 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
     }
     const int n = B.ntot;
     // only single-box passes carry an activity mask (the batched forms pass
-    // none); its cell flags go to chunk_count, which k_segsort then turns
-    // into item counts
-    const bool masked = !B.boxes && B.one.active != nullptr && chunk_count;
-    if (masked && (rc = fill_enqueue(ctx, chunk_count, 0, B.ctot)))
+    // none); its cell flags go to chunk_count and its active counts to
+    // tcount, which k_segsort then turns into item counts
+    const bool masked = !B.boxes && B.one.active != nullptr;
+    if (masked && !(chunk_count && tcount))
+        return sr_fail(ctx, SR_EINVAL, "an activity mask needs item and target counts");
+    if (masked && ((rc = fill_enqueue(ctx, chunk_count, 0, B.ctot)) ||
+                   (rc = fill_enqueue(ctx, tcount, 0, B.ctot))))
         return rc;
     if (n > 0) {
         if (masked)
             hipLaunchKernelGGL(k_cellid<true>, dim3(blocks_for(n, kCellidBlock)), dim3(kBlock), 0,
-                               ctx->stream, B, s.cid, s.slot, s.count, ctx->status, chunk_count);
+                               ctx->stream, B, s.cid, s.slot, s.count, ctx->status, chunk_count,
+                               tcount);
         else
             hipLaunchKernelGGL(k_cellid<false>, dim3(blocks_for(n, kCellidBlock)), dim3(kBlock),
-                               0, ctx->stream, B, s.cid, s.slot, s.count, ctx->status, nullptr);
+                               0, ctx->stream, B, s.cid, s.slot, s.count, ctx->status, nullptr,
+                               nullptr);
         if ((rc = sr_check_launch(ctx, "k_cellid")))
             return rc;
     }
@@ -889,7 +916,7 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
         return rc;
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
-                           s.cid, s.slot, n, offsets, perm);
+                           s.cid, s.slot, n, offsets, masked ? B.one.active : nullptr, perm);
         if ((rc = sr_check_launch(ctx, "k_scatter")))
             return rc;
     }
@@ -897,7 +924,7 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
     int *inv = sorted ? s.slot : nullptr;
     hipLaunchKernelGGL(k_segsort, dim3(blocks_for(B.ctot, kBlock / 64 * kSegGroup)), dim3(kBlock), 0,
                        ctx->stream, B, offsets, perm, s.large_list, s.large_count, inv,
-                       chunk_count);
+                       chunk_count, masked ? tcount : nullptr);
     if ((rc = sr_check_launch(ctx, "k_segsort")))
         return rc;
     if (n > kLargeCell) {
@@ -955,5 +982,5 @@ extern "C" int sr_bin(sr_ctx *ctx, const float *x, const float *y, const float *
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
     bin_layout(b, n, B.ctot, 1, s);
-    return bin_enqueue(ctx, B, s, cell_offsets, perm, nullptr, nullptr);
+    return bin_enqueue(ctx, B, s, cell_offsets, perm, nullptr, nullptr, nullptr);
 }

@@ -353,7 +353,9 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
 }
 
 // Work items of a block of 256 cells: each thread takes one cell's chunk
-// count and stencil size (sub-items for cells flagged kFineFlag), the block
+// count and stencil size (sub-items for cells flagged kFineFlag; with target
+// counts, a masked pass, the chunks cover the cell's first tcount[c] slots,
+// where its active particles sit), the block
 // reserves its item range with one atomic on *n_items, then all threads
 // write the block's items, thread j the items j, j + 256, ... (the cell of an
 // item found by a binary search over the block's running item counts).  The
@@ -362,6 +364,7 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
 // sub-items added in order.
 __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ offsets,
                                                const int *__restrict__ chunk_count,
+                                               const int *__restrict__ tcount,
                                                int4 *__restrict__ items,
                                                int *__restrict__ item_cost,
                                                int *__restrict__ n_items)
@@ -378,6 +381,8 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
     long long src = 0;
     if (q > 0) {
         src = cell_stencil(B, offsets, c, &box, &b, &len);
+        if (tcount)
+            len = tcount[c];  // the active particles, sorted to the front of the cell
         if (cc & kFineFlag) {
             const long long k = (src + kSplitSources - 1) / kSplitSources;
             ns = k < 1 ? 1 : (k > kMaxSrcSplit ? kMaxSrcSplit : (int)k);
@@ -610,6 +615,7 @@ void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s, 
     s.queue = b.take<int>(1);
     s.mom_part = b.take<double>((size_t)(nb > 0 ? nb : 1) * kRedBlocks * 3);
     s.part = masked ? b.take<float4>(nn * kMaxSrcSplit) : nullptr;
+    s.tcount = masked ? b.take<int>((size_t)ctot) : nullptr;
 }
 
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly)
@@ -689,10 +695,10 @@ int lpt_sort_enqueue(sr_ctx *ctx, const int4 *items, const int *item_cost, const
 static int bin_items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, int order)
 {
     int rc;
-    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count)))
+    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count, s.tcount)))
         return rc;
     hipLaunchKernelGGL(k_items, dim3((B.ctot + 255) / 256), dim3(256), 0, ctx->stream, B,
-                       s.offsets, s.chunk_count, s.items, s.item_cost, s.bin.n_items);
+                       s.offsets, s.chunk_count, s.tcount, s.items, s.item_cost, s.bin.n_items);
     if ((rc = sr_check_launch(ctx, "k_items")))
         return rc;
     if (order == 1)

@@ -89,7 +89,10 @@ struct BoxDesc {
     int pbase, n, cbase, _pad;
     const float *x, *y, *z, *m;   // positions, or cell offsets when g.split
     const int *cell3;             // split coordinates: packed chaining cells
-    const unsigned char *active;  // optional: 0 inactive, 1 active, 2 active in a cell cut into finer items; only cells holding an active particle get items
+    // optional, single-box passes: 0 inactive, 1 active, 2 active and its
+    // cell cut into finer items; only active particles are targets (every
+    // particle stays a source) and only their accelerations are written
+    const unsigned char *active;
     float *ax, *ay, *az;
 };
 
@@ -203,6 +206,7 @@ struct ForceScratch {
     int *queue;       // [1] persistent work counter
     double *mom_part; // [nb * kRedBlocks * 3]
     float4 *part;     // [kMaxSrcSplit * ntot] sub-item partial sums (masked passes), or null
+    int *tcount;      // [ctot] active targets per cell (masked passes), or null
 };
 
 constexpr int kRedBlocks = 512;    // FP64 reduction blocks per box (at most)
@@ -228,7 +232,7 @@ void sr_timing_mark(sr_ctx *ctx, int rec, int which);
 // Binning (sr_bin.hip)
 void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s);
 int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, int *perm,
-                float4 *sorted, int *chunk_count);
+                float4 *sorted, int *chunk_count, int *tcount);
 void scan_layout(Bump &b, int m, int **part);
 int scan_enqueue(sr_ctx *ctx, const int *in, int m, int *part, int *out, int *flag);
 int fill_enqueue(sr_ctx *ctx, int *p, int value, int64_t count);

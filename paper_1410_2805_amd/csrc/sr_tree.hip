@@ -729,7 +729,7 @@ int tree_prep(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const TreeScra
 {
     int rc;
     const int n = B.ntot;
-    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, nullptr)))
+    if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, nullptr, nullptr)))
         return rc;
     if ((rc = fill_enqueue(ctx, t.flag, 0, n > 0 ? n : 1)) || (rc = fill_enqueue(ctx, t.flag0, 0, 1)))
         return rc;
