@@ -113,7 +113,9 @@ int sr_grid_dims(const sr_box *box, double cell, int32_t dims[3], int64_t *n_cel
  * particles in this geometry; with_force = 2: an sr_ksk_step with multilevel
  * subcycles (its short-range passes with an activity mask, sub-item sums,
  * levels and counts).  A fixed arena of at least this size never returns
- * SR_ENOMEM for such a call. */
+ * SR_ENOMEM for such a call.  Up to 2^22 particles a force pass may cut the
+ * work of dense cells into sub-items whose partial sums take 112 bytes per
+ * particle (about 210 bytes per particle in all; about 41 beyond). */
 int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force, size_t *bytes);
 
 /* Chaining-mesh binning (a stable counting sort by cell).
@@ -163,9 +165,10 @@ int sr_force(sr_ctx *ctx, const float *x, const float *y, const float *z, const 
  * call uses one fixed device array of sr_force_static_capacity() bytes
  * (128 MiB) per GPU, held from the library's load until the process ends;
  * this call allocates nothing (no hipMalloc, no events, no library
- * allocation).  About 40 bytes per particle plus 12 per chaining cell are
- * needed: a 128^3-particle box with 3-unit cells fits; a call needing more
- * returns SR_ENOMEM with a message and enqueues nothing.  No timing record
+ * allocation).  The scratch is sr_force's (sr_scratch_bytes with
+ * with_force = 1): about 210 bytes per particle plus some per chaining cell
+ * up to 2^22 particles, so that a box of 80^3 particles fits; a call needing
+ * more returns SR_ENOMEM with a message and enqueues nothing.  No timing record
  * is taken (sr_timing_collect does not see these calls).
  * Concurrency: every call on one GPU shares that GPU's array, whatever its
  * context or stream, and the array keeps the last call's contents (each

@@ -864,6 +864,7 @@ void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
     s.scan_flag = b.take<int>(1);
     s.lpt = b.take<int>(64);
     s.n_items = b.take<int>(1);
+    s.n_heads = b.take<int>(1);
 }
 
 // Enqueue the whole binning pass.  sorted and chunk_count may be NULL (then
@@ -887,6 +888,8 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
         cl.n[4] = 64;
         cl.p[5] = s.n_items;
         cl.n[5] = 1;
+        cl.p[6] = s.n_heads;
+        cl.n[6] = 1;
         if ((rc = clear_enqueue(ctx, cl)))
             return rc;
     }

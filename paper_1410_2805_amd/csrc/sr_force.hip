@@ -149,8 +149,10 @@ __device__ __forceinline__ void process_item(const Batch &B, const int4 item,
             acy += o.y;
             acz += o.z;
         }
-        const int nsub = item_nsub(item);
-        float4 *pp = nsub > 1 ? subsums + (size_t)item_sub(item) * B.ntot : nullptr;
+        // sub-item 0 writes the accelerations as a whole item does, sub-item
+        // sk > 0 its partial sums to plane sk - 1
+        const int sub = item_sub(item);
+        float4 *pp = sub > 0 ? subsums + (size_t)(sub - 1) * B.ntot : nullptr;
         if (pp) {
             pp[kb + t] = pas ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(acx, acy, acz, 0.f);
         } else {
@@ -191,9 +193,9 @@ __device__ __forceinline__ int item_position(int b)
     return ((j >> 6) * 8 + xcd) * 64 + (j & 63);
 }
 
-// One workgroup per item: the grid covers the item bound (a multiple of 512),
-// or, for passes with sub-items, at most kMaskedGrid workgroups that also
-// serve positions + k gridDim.
+// One workgroup per item: the grid covers the chunk bound (a multiple of 512;
+// at most kMaskedGrid workgroups in masked passes), and a workgroup also
+// serves positions + k gridDim when sub-items make more items than that.
 __global__ __launch_bounds__(64) void k_force(Batch B, const int4 *__restrict__ items,
                                               const int *__restrict__ n_items,
                                               const float4 *__restrict__ sorted,
@@ -210,31 +212,33 @@ __global__ __launch_bounds__(64) void k_force(Batch B, const int4 *__restrict__ 
                      subsums);
 }
 
-// Adds the partial sums of the sub-items of every chunk, in sub-item order,
-// and writes the chunk's accelerations (the first sub-item's workgroup;
-// passive targets' partials are exact zeros).
-__global__ __launch_bounds__(64) void k_subsum(Batch B, const int4 *__restrict__ items,
-                                               const int *__restrict__ n_items,
-                                               const int *__restrict__ perm,
-                                               const float4 *__restrict__ subsums)
+// Adds the partial sums of the sub-items of every chunk cut into sub-items
+// (heads: each chunk's first sub-item), in sub-item order -- sub-item 0's
+// sums are in the outputs already -- and writes the chunk's accelerations
+// (passive targets' partials are exact zeros).
+// Thread g of the grid-stride loop takes target g % kChunk2 of head g / kChunk2.
+__global__ __launch_bounds__(256) void k_subsum(Batch B, const int4 *__restrict__ heads,
+                                                const int *__restrict__ n_heads,
+                                                const int *__restrict__ perm,
+                                                const float4 *__restrict__ subsums)
 {
-    const int n = *n_items;
-    for (int pos = blockIdx.x; pos < n; pos += gridDim.x) {
-        const int4 item = items[pos];
+    const long long n = (long long)*n_heads * kChunk2;
+    for (long long g = (long long)blockIdx.x * 256 + threadIdx.x; g < n;
+         g += (long long)gridDim.x * 256) {
+        const int4 item = heads[g / kChunk2];
+        const int t = (int)(g % kChunk2);
         const int ns = item_nsub(item);
-        if (ns == 1 || item_sub(item) != 0)
-            continue;
         const BoxDesc &d = box_at(B, item_box(item));
-        for (int t = threadIdx.x; t < item.z; t += 64) {
+        if (t < item.z) {
             const int slot = item.y + t;
-            float ax = 0.f, ay = 0.f, az = 0.f;
-            for (int k = 0; k < ns; ++k) {
-                const float4 v = subsums[(size_t)k * B.ntot + slot];
+            const int orig = perm[slot] - d.pbase;
+            float ax = d.ax[orig], ay = d.ay[orig], az = d.az[orig];
+            for (int k = 1; k < ns; ++k) {
+                const float4 v = subsums[(size_t)(k - 1) * B.ntot + slot];
                 ax += v.x;
                 ay += v.y;
                 az += v.z;
             }
-            const int orig = perm[slot] - d.pbase;
             d.ax[orig] = ax;
             d.ay[orig] = ay;
             d.az[orig] = az;
@@ -353,21 +357,26 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
 }
 
 // Work items of a block of 256 cells: each thread takes one cell's chunk
-// count and stencil size (sub-items for cells flagged kFineFlag; with target
-// counts, a masked pass, the chunks cover the cell's first tcount[c] slots,
-// where its active particles sit), the block
+// count and stencil size (chunks of cells flagged kFineFlag are cut into
+// sub-items by their source count; with split, the other chunks of boxes
+// that box_splits admits by their pair count; with target counts, a masked
+// pass, the chunks cover the cell's first tcount[c] slots, where its active
+// particles sit), the block
 // reserves its item range with one atomic on *n_items, then all threads
 // write the block's items, thread j the items j, j + 256, ... (the cell of an
 // item found by a binary search over the block's running item counts).  The
 // order of the items depends on which block reserves first; no result does:
 // every target is summed in a fixed order, by one item or by its chunk's
-// sub-items added in order.
+// sub-items added in order.  The first sub-item of every cut chunk is also
+// appended to heads, for k_subsum.
 __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ offsets,
                                                const int *__restrict__ chunk_count,
-                                               const int *__restrict__ tcount,
+                                               const int *__restrict__ tcount, int split,
                                                int4 *__restrict__ items,
                                                int *__restrict__ item_cost,
-                                               int *__restrict__ n_items)
+                                               int *__restrict__ n_items,
+                                               int4 *__restrict__ heads,
+                                               int *__restrict__ n_heads)
 {
     __shared__ int wsum[4];
     __shared__ int base;
@@ -385,6 +394,9 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
             len = tcount[c];  // the active particles, sorted to the front of the cell
         if (cc & kFineFlag) {
             const long long k = (src + kSplitSources - 1) / kSplitSources;
+            ns = k < 1 ? 1 : (k > kMaxSrcSplit ? kMaxSrcSplit : (int)k);
+        } else if (split && box_splits(box_at(B, box).n)) {
+            const long long k = (src * ((len + q - 1) / q) + kSplitPairs - 1) / kSplitPairs;
             ns = k < 1 ? 1 : (k > kMaxSrcSplit ? kMaxSrcSplit : (int)k);
         }
     }
@@ -423,9 +435,12 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
         const int r = j - (s_end[lo] - qq * nn);
         const int k = r / nn;
         int bucket;
-        items[base + j] = cell_item(blockIdx.x * 256 + lo, s_box[lo], s_b[lo], s_len[lo], qq, k,
-                                    nn, r - k * nn, s_src[lo], &bucket);
+        const int4 it = cell_item(blockIdx.x * 256 + lo, s_box[lo], s_b[lo], s_len[lo], qq, k,
+                                  nn, r - k * nn, s_src[lo], &bucket);
+        items[base + j] = it;
         item_cost[base + j] = bucket;
+        if (nn > 1 && r == k * nn)
+            heads[atomicAdd(n_heads, 1)] = it;
     }
 }
 
@@ -577,6 +592,7 @@ __global__ __launch_bounds__(256) void k_momentum_final(const double *__restrict
 }
 
 constexpr unsigned kMaskedGrid = 65536;  // workgroups of a masked pass at most (a multiple of 512)
+constexpr unsigned kSubsumGrid = 256;    // workgroups of k_subsum (256 threads each)
 
 unsigned grid_for_items(int64_t ub)
 {
@@ -590,20 +606,22 @@ int lpt_blocks(int64_t ub)
 
 }  // namespace
 
-int64_t item_bound(int64_t ntot, int64_t ctot, bool masked)
+int64_t item_bound(int64_t ntot, int64_t ctot, bool split)
 {
     int64_t nonempty = ntot < ctot ? ntot : ctot;
-    // plain: at most max(ceil(n / 64), n / 16) chunks per cell (chunks_for);
-    // masked: flagged cells take ceil(n / kFineChunk) <= n / 32 + 1 chunks of
-    // at most kMaxSrcSplit sub-items each, and kMaxSrcSplit (n / 32 + 1) also
-    // bounds the plain count
-    return masked ? kMaxSrcSplit * (nonempty + ntot / 32 + 1) : nonempty + ntot / 16 + 1;
+    // at most max(ceil(n / 64), n / 16) <= n / 16 + 1 chunks per cell
+    // (mesh_chunks_for; flagged cells take ceil(n / kFineChunk) <= n / 32 + 1),
+    // each of at most kMaxSrcSplit sub-items when chunks may be cut
+    const int64_t chunks = nonempty + ntot / 16 + 1;
+    return split ? kMaxSrcSplit * chunks : chunks;
 }
 
-void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s, bool masked)
+void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s, bool masked,
+                  bool split_ok)
 {
     size_t nn = (size_t)(ntot > 0 ? ntot : 1);
-    const int64_t ub = item_bound(ntot, ctot, masked);
+    const bool split = masked || split_ok;
+    const int64_t ub = item_bound(ntot, ctot, split);
     bin_layout(b, ntot, ctot, nb, s.bin);
     s.offsets = b.take<int>((size_t)ctot + 1);
     s.perm = b.take<int>(nn);
@@ -614,7 +632,8 @@ void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s, 
     s.items_lpt = b.take<int4>((size_t)ub);
     s.queue = b.take<int>(1);
     s.mom_part = b.take<double>((size_t)(nb > 0 ? nb : 1) * kRedBlocks * 3);
-    s.part = masked ? b.take<float4>(nn * kMaxSrcSplit) : nullptr;
+    s.part = split ? b.take<float4>(nn * (kMaxSrcSplit - 1)) : nullptr;
+    s.heads = split ? b.take<int4>((size_t)item_bound(ntot, ctot)) : nullptr;
     s.tcount = masked ? b.take<int>((size_t)ctot) : nullptr;
 }
 
@@ -698,7 +717,8 @@ static int bin_items_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s,
     if ((rc = bin_enqueue(ctx, B, s.bin, s.offsets, s.perm, s.sorted, s.chunk_count, s.tcount)))
         return rc;
     hipLaunchKernelGGL(k_items, dim3((B.ctot + 255) / 256), dim3(256), 0, ctx->stream, B,
-                       s.offsets, s.chunk_count, s.tcount, s.items, s.item_cost, s.bin.n_items);
+                       s.offsets, s.chunk_count, s.tcount, s.part != nullptr ? 1 : 0, s.items,
+                       s.item_cost, s.bin.n_items, s.heads, s.bin.n_heads);
     if ((rc = sr_check_launch(ctx, "k_items")))
         return rc;
     if (order == 1)
@@ -735,18 +755,19 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
                                B, items, n_items, s.sorted, s.offsets, s.perm, s.bin.mass_mixed,
                                fp, s.queue);
         } else {
-            // a pass with sub-items (masked) has a loose item bound: a capped
-            // grid walks it
-            unsigned grid = grid_for_items(item_bound(B.ntot, B.ctot, s.part != nullptr));
-            if (s.part && grid > kMaskedGrid)
+            // with sub-items the item bound is loose: the grid covers the
+            // chunk bound (at most kMaskedGrid workgroups in masked passes,
+            // which have few items) and walks the rest
+            unsigned grid = grid_for_items(item_bound(B.ntot, B.ctot));
+            if (s.tcount && grid > kMaskedGrid)
                 grid = kMaskedGrid;
             hipLaunchKernelGGL(k_force, dim3(grid), dim3(64), 0, ctx->stream, B, items, n_items,
                                s.sorted, s.offsets, s.perm, s.bin.mass_mixed, fp, s.part);
             if (s.part) {
                 if ((rc = sr_check_launch(ctx, "k_force")))
                     return rc;
-                hipLaunchKernelGGL(k_subsum, dim3(grid), dim3(64), 0, ctx->stream, B, items,
-                                   n_items, s.perm, s.part);
+                hipLaunchKernelGGL(k_subsum, dim3(kSubsumGrid), dim3(256), 0, ctx->stream, B,
+                                   s.heads, s.bin.n_heads, s.perm, s.part);
             }
         }
         if ((rc = sr_check_launch(ctx, "k_force")))
@@ -830,7 +851,7 @@ int force_split_masked(sr_ctx *ctx, const int32_t *cell3, const float *ox, const
     Bump sz{nullptr, 0, 0};
     ForceScratch s;
     const bool masked = active != nullptr;
-    force_layout(sz, n, B.ctot, 1, s, masked);
+    force_layout(sz, n, B.ctot, 1, s, masked, box_splits(n));
     if (bytes) {
         *bytes = sz.off;
         return SR_OK;
@@ -840,7 +861,7 @@ int force_split_masked(sr_ctx *ctx, const int32_t *cell3, const float *ox, const
     if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
-    force_layout(b, n, B.ctot, 1, s, masked);
+    force_layout(b, n, B.ctot, 1, s, masked, box_splits(n));
     const ForceParams fp = make_params(r_max, eps, poly);
     const int rec = sr_timing_begin(ctx);
     return force_enqueue(ctx, B, s, fp, ctx->order, ctx->persistent, momentum3, rec);
@@ -870,7 +891,7 @@ extern "C" int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int w
     Bump sz{nullptr, 0, 0};
     if (with_force) {
         ForceScratch s;
-        force_layout(sz, n, g.ncell, 1, s, with_force == 2);
+        force_layout(sz, n, g.ncell, 1, s, with_force == 2, box_splits(n));
         if (with_force == 2) {
             // the multilevel step's levels, activity mask and cell counts
             // (sr_ksk_step lays them out after the force pass)
@@ -909,11 +930,11 @@ extern "C" int sr_force(sr_ctx *ctx, const float *x, const float *y, const float
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
     Bump sz{nullptr, 0, 0};
     ForceScratch s;
-    force_layout(sz, n, B.ctot, 1, s);
+    force_layout(sz, n, B.ctot, 1, s, false, box_splits(n));
     if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
-    force_layout(b, n, B.ctot, 1, s);
+    force_layout(b, n, B.ctot, 1, s, false, box_splits(n));
     const ForceParams fp = make_params(r_max, eps, poly);
     const int rec = sr_timing_begin(ctx);
     return force_enqueue(ctx, B, s, fp, ctx->order, ctx->persistent, momentum3, rec);
@@ -939,11 +960,11 @@ extern "C" int sr_pair_stats(sr_ctx *ctx, const float *x, const float *y, const 
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
     Bump sz{nullptr, 0, 0};
     ForceScratch s;
-    force_layout(sz, n, B.ctot, 1, s);
+    force_layout(sz, n, B.ctot, 1, s, false, false);  // whole chunks
     if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
-    force_layout(b, n, B.ctot, 1, s);
+    force_layout(b, n, B.ctot, 1, s, false, false);
     if ((rc = bin_items_enqueue(ctx, B, s, 0)))
         return rc;
     // eps = 0 so that se = s and the test is s < r_max^2

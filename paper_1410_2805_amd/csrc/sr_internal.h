@@ -184,10 +184,11 @@ struct BinScratch {
     int *scan_flag;   // [1] last-block counter of the scans (kept at 0)
     int *lpt;         // [64] key totals and cursors of the longest-first item order
     int *n_items;     // [1] force work items appended by k_items
+    int *n_heads;     // [1] chunks cut into sub-items, appended by k_items
 };
 
-// Up to six int buffers zeroed by one kernel launch.
-constexpr int kClear = 6;
+// Up to seven int buffers zeroed by one kernel launch.
+constexpr int kClear = 7;
 struct ClearList {
     int *p[kClear];
     int64_t n[kClear];
@@ -205,7 +206,8 @@ struct ForceScratch {
     int4 *items_lpt;  // [item bound] items by decreasing cost bucket
     int *queue;       // [1] persistent work counter
     double *mom_part; // [nb * kRedBlocks * 3]
-    float4 *part;     // [kMaxSrcSplit * ntot] sub-item partial sums (masked passes), or null
+    float4 *part;     // [(kMaxSrcSplit - 1) * ntot] partial sums of sub-items 1.., or null
+    int4 *heads;      // [chunk bound] first sub-items of the chunks cut into sub-items
     int *tcount;      // [ctot] active targets per cell (masked passes), or null
 };
 
@@ -241,9 +243,12 @@ int clear_enqueue(sr_ctx *ctx, const ClearList &cl);
 // Force pass (sr_force.hip)
 // Items of a pass at most; masked: a pass with an activity mask, whose
 // flagged cells may take finer items and sub-items.
-int64_t item_bound(int64_t ntot, int64_t ctot, bool masked = false);
-void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s,
-                  bool masked = false);
+int64_t item_bound(int64_t ntot, int64_t ctot, bool split = false);
+// masked: a pass with an activity mask (its flagged cells are cut into
+// sub-items); split_ok: some box of the pass may cut its chunks
+// (box_splits).  Either gives the pass sub-item storage.
+void force_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, ForceScratch &s, bool masked,
+                  bool split_ok);
 int check_box_args(sr_ctx *ctx, const sr_box *box, double cell, float r_max, int xsplit,
                    Geom *g);
 int check_force_params(sr_ctx *ctx, float r_max, float eps, const float *poly);
@@ -391,13 +396,26 @@ __device__ __forceinline__ int mesh_chunks(int n)
 }
 
 // Work items.  A cell of n targets is cut into q nearly equal chunks [k n /
-// q, (k + 1) n / q); a chunk is one item, or, in cells flagged for finer
-// items (multilevel passes over few dense cells), ns sub-items that take
+// q, (k + 1) n / q); a chunk is one item, or ns sub-items that take
 // consecutive parts [sk T / ns, (sk + 1) T / ns) of the T stencil sources,
-// so that one dense cell's pairs spread over more wavefronts.  A sub-item
-// leaves partial sums, which a second pass adds in sub-item order.
+// so that the pairs of a dense cell spread over more wavefronts and no
+// single wavefront holds up the end of the pass: chunks of cells flagged for
+// finer items (multilevel passes over few dense cells) by their source
+// count, other chunks by their pair count.  A sub-item leaves partial sums,
+// which a second pass adds in sub-item order.
 constexpr int kMaxSrcSplit = 8;       // sub-items per chunk at most
-constexpr int kSplitSources = 4096;   // stencil sources per sub-item, about
+constexpr int kSplitSources = 4096;   // stencil sources per sub-item, about (finer items)
+constexpr long long kSplitPairs = 1 << 20;  // target-source pairs per sub-item, about (other chunks)
+constexpr int64_t kSplitMaxN = 1 << 22;     // boxes of at most this many particles cut other chunks
+
+// Whether the chunks of a box of n particles (other than those of cells
+// flagged for finer items) may be cut into sub-items: a property of the box
+// alone, so that a box gives the same sums alone and in a batch.  Larger
+// boxes have enough items to keep every wavefront busy to the end.
+__host__ __device__ inline bool box_splits(int64_t n)
+{
+    return n <= kSplitMaxN;
+}
 constexpr int kFineFlag = 1 << 30;    // chunk_count bit: cell flagged for finer items
 constexpr int kMaxBatchBoxes = 1 << 17;
 

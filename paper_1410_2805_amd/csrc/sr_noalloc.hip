@@ -63,7 +63,7 @@ extern "C" int sr_force_static(sr_ctx *ctx, const float *x, const float *y, cons
         return sr_fail(ctx, SR_EINVAL, "NULL mass or output pointer");
     Bump sz{nullptr, 0, 0};
     ForceScratch s;
-    force_layout(sz, n, B.ctot, 1, s);
+    force_layout(sz, n, B.ctot, 1, s, false, box_splits(n));
     if (sz.off > kStaticScratchBytes)
         return sr_fail(ctx, SR_ENOMEM,
                        "sr_force_static: %zu scratch bytes needed, the fixed array holds %zu "
@@ -79,7 +79,7 @@ extern "C" int sr_force_static(sr_ctx *ctx, const float *x, const float *y, cons
     if (hipSetDevice(ctx->device) != hipSuccess)
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
     Bump b{(char *)ptr, 0, kStaticScratchBytes};
-    force_layout(b, n, B.ctot, 1, s);
+    force_layout(b, n, B.ctot, 1, s, false, box_splits(n));
     const ForceParams fp = make_params(r_max, eps, poly);
     // no timing record: its events would be created on demand
     return force_enqueue(ctx, B, s, fp, ctx->order, ctx->persistent, momentum3, -1);

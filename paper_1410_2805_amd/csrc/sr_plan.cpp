@@ -185,12 +185,14 @@ extern "C" int sr_plan_create(sr_ctx *ctx, const sr_batch_box *boxes, int nboxes
     if (rc)
         return rc;
     int64_t ntot = 0;
+    bool split_ok = false;  // some box may cut its chunks into sub-items
     for (int b = 0; b < nboxes; ++b) {
         const sr_batch_box &bx = boxes[b];
         if (bx.n < 0 || (bx.n > 0 && (!bx.x || !bx.y || !bx.z || !bx.mass || !bx.ax ||
                                       !bx.ay || !bx.az)))
             return sr_fail(ctx, SR_EINVAL, "box %d: bad size or NULL pointer", b);
         ntot += bx.n;
+        split_ok = split_ok || box_splits(bx.n);
     }
     if (ntot > 2147483647LL)
         return sr_fail(ctx, SR_EINVAL, "too many particles in the batch");
@@ -228,7 +230,7 @@ extern "C" int sr_plan_create(sr_ctx *ctx, const sr_batch_box *boxes, int nboxes
     sz.take<int>(nboxes + 1);
     sz.take<int>(nboxes + 1);
     ForceScratch tmp;
-    force_layout(sz, ntot, ctot_max, nboxes, tmp);
+    force_layout(sz, ntot, ctot_max, nboxes, tmp, false, split_ok);
     void *mem = nullptr;
     if (hipMalloc(&mem, sz.off) != hipSuccess) {
         (void)hipGetLastError();
@@ -240,7 +242,7 @@ extern "C" int sr_plan_create(sr_ctx *ctx, const sr_batch_box *boxes, int nboxes
     p->d_boxes = b.take<BoxDesc>(nboxes);
     p->d_pstart = b.take<int>(nboxes + 1);
     p->d_cstart = b.take<int>(nboxes + 1);
-    force_layout(b, ntot, ctot_max, nboxes, p->s);
+    force_layout(b, ntot, ctot_max, nboxes, p->s, false, split_ok);
     if ((rc = configure(p, p->tuning))) {
         sr_plan_destroy(p);
         return rc;

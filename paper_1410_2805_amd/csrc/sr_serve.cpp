@@ -155,7 +155,7 @@ size_t scratch_need(const sr_server *S, int64_t ntot, int64_t ctot, int nb)
 {
     Bump sz{nullptr, 0, 0};
     ForceScratch s;
-    force_layout(sz, ntot, ctot, nb, s);
+    force_layout(sz, ntot, ctot, nb, s, false, true);  // any request may cut its chunks
     return sz.off;
 }
 
@@ -386,7 +386,7 @@ extern "C" int sr_server_tick(sr_server *S, int *n_active)
     B.ctot = cb;
     Bump bs{S->scratch, 0, S->scratch_cap};
     ForceScratch fs;
-    force_layout(bs, pb, cb, nb, fs);
+    force_layout(bs, pb, cb, nb, fs, false, true);
     if (bs.off > S->scratch_cap)
         return sr_fail(ctx, SR_ENOMEM, "scratch overflow (admission bug)");
     if ((rc = slot_update_enqueue(ctx, ds, dp, nb, pb, 0)))

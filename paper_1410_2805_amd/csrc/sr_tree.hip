@@ -780,12 +780,12 @@ int tree_setup(sr_ctx *ctx, const float *x, const float *y, const float *z, cons
     if (hipSetDevice(ctx->device) != hipSuccess)
         return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
     Bump sz{nullptr, 0, 0};
-    force_layout(sz, n, B.ctot, 1, s);
+    force_layout(sz, n, B.ctot, 1, s, false, false);  // no work-item sub-items
     tree_layout(sz, n, B.ctot, t);
     if ((rc = sr_arena_reserve(ctx, sz.off)))
         return rc;
     Bump b{ctx->arena, 0, ctx->arena_cap};
-    force_layout(b, n, B.ctot, 1, s);
+    force_layout(b, n, B.ctot, 1, s, false, false);
     tree_layout(b, n, B.ctot, t);
     return SR_OK;
 }

@@ -39,11 +39,19 @@ def test_grid_dims_and_scratch():
         sr.sr_grid_dims(sr.Box.make(10.0), 0.0)
     b1 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, True)
     b0 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, False)
-    # the multilevel step: masked passes (sub-item sums of 8 x 16 B per
-    # particle) plus its levels, mask and cell counts
+    # up to 2^22 particles a force pass may cut long chunks into sub-items:
+    # partial sums of 7 x 16 B per particle
+    assert b1 > b0 + 7 * 16 * 2 ** 21
+    assert b0 > 2 ** 21 * 8
+    # the multilevel step adds target counts, levels, mask and cell counts
     b2 = sr.sr_scratch_bytes(sr.Box.make(128.0), 3.0, 2 ** 21, 2)
-    assert b2 > b1 + 8 * 16 * 2 ** 21
-    assert b1 > b0 > 2 ** 21 * 8
+    assert b2 > b1 + 2 * 2 ** 21
+    # beyond 2^22 particles only the masked passes of the multilevel step do
+    big0 = sr.sr_scratch_bytes(sr.Box.make(256.0), 3.0, 2 ** 23, False)
+    big1 = sr.sr_scratch_bytes(sr.Box.make(256.0), 3.0, 2 ** 23, True)
+    big2 = sr.sr_scratch_bytes(sr.Box.make(256.0), 3.0, 2 ** 23, 2)
+    assert big0 < big1 < big0 + 48 * 2 ** 23
+    assert big2 > big1 + 7 * 16 * 2 ** 23
     # box sides are bounded so that tile padding (at 1e6) stays beyond every cutoff
     assert sr.sr_scratch_bytes(sr.Box.make((131072.0, 12.0, 12.0)), 3.0, 1000, True) > 0
     with pytest.raises(sr.SRError):

@@ -133,6 +133,33 @@ def test_item_order_and_persistent(sr, ctx, poly, order, persistent):
     check_accel(a1, _ref(p, poly), "order %d persistent %d" % (order, persistent))
 
 
+def test_dense_cells_cut_into_sub_items(sr, ctx, poly):
+    """An open box of 300,000 particles whose densest cells hold up to 24,000:
+    their chunks exceed the pair count of one work item and are cut into
+    sub-items over the stencil sources, whose partial sums are added in
+    sub-item order.  The result is bitwise reproducible, the same under
+    every item order and persistence setting, and within the oracle's bound
+    on targets drawn from the densest cells."""
+    p = W.nfw_share(300_000, 40.0, 13)
+    before = ctx.get_tuning()
+    try:
+        a0, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+        a1, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+        ctx.set_tuning(order=0, persistent=1)
+        a2, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+    finally:
+        ctx.set_tuning(**before)
+    assert np.array_equal(a0, a1) and np.array_equal(a0, a2)
+    _, _, cid = O.bin(p.x, p.y, p.z, p.L, 3.0)
+    counts = np.bincount(cid)
+    dense = np.nonzero(counts[cid] >= np.sort(counts)[-20])[0]
+    rng = np.random.default_rng(79)
+    tg = np.unique(np.concatenate([rng.choice(p.n, 256, replace=False),
+                                   rng.choice(dense, 256, replace=False)]))
+    st = check_accel(a0[tg], _ref(p, poly, targets=tg), "dense sub-items")
+    print("dense sub-items", st)
+
+
 def test_determinism_and_momentum(sr, ctx, poly):
     p = W.uniform(20000, 28.0, 13)
     a1, m1 = _gpu_force(sr, ctx, p, 3.0, poly, momentum=True)

@@ -118,9 +118,10 @@ def test_alone_equals_mix_bitwise(sr, ctx, poly):
 
 
 def test_admission_budget_and_queueing(sr, ctx, poly):
-    # 64 MiB: 32 MiB of state; a 64^3 request (68 B/particle: 17 MiB) fits,
-    # two at once do not; a 96^3 one never fits.
-    srv = sr.Server(ctx, 64 << 20, 8, R_MAX, EPS, poly, CELL)
+    # 128 MiB: 64 MiB of state and 64 MiB of pass scratch; a 64^3 request
+    # (68 B/particle of state, 17 MiB; about 210 B/particle of scratch with
+    # sub-item sums, 52 MiB) fits, two at once do not; a 96^3 one never fits.
+    srv = sr.Server(ctx, 128 << 20, 8, R_MAX, EPS, poly, CELL)
     try:
         with pytest.raises(sr.SRError) as e:
             _submit(sr, srv, 96, 2, _box(96, 1))

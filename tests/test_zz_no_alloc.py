@@ -1,6 +1,7 @@
 """sr_force_static (fixed device scratch, no allocation) against sr_force and
-the FP64 oracle, through the C ABI: two calls in a row on one GPU, the second
-with a smaller box, each bitwise equal to sr_force at the same tuning."""
+the FP64 oracle, through the C ABI: calls in a row on one GPU, each with a
+smaller box than the one before, each bitwise equal to sr_force at the same
+tuning."""
 import numpy as np
 import pytest
 import torch
@@ -38,8 +39,10 @@ def test_static_scratch_matches_sr_force():
     poly = gridfit.poly_coeffs()
     ctx = S.Context(0)
     try:
-        # a periodic box, then a smaller clustered open box with a skin
-        cases = [W.uniform(110_592, 48.0, 11), W.nfw_share(8000, 20.0, 12, skin=3.0)]
+        # a clustered open box whose dense cells are cut into sub-items, a
+        # smaller periodic box, then a smaller clustered open box with a skin
+        cases = [W.nfw_share(300_000, 40.0, 13), W.uniform(110_592, 48.0, 11),
+                 W.nfw_share(8000, 20.0, 12, skin=3.0)]
         for p in cases:
             print("case: n=%d L=%g periodic=%s" % (p.n, p.L, p.periodic), flush=True)
             a_s, m_s, a_p, m_p = _static_and_plain(S, ctx, p, poly)
@@ -58,12 +61,12 @@ def test_static_scratch_too_large_is_refused():
     poly = gridfit.poly_coeffs()
     ctx = S.Context(0)
     try:
-        n = 4_000_000  # about 160 MB of scratch: beyond the fixed array
-        assert S.sr_force_static_capacity() < 40 * n
+        n = 4_000_000  # about 840 MB of scratch: beyond the fixed array
+        box = S.Box.make(160.0)
+        assert S.sr_force_static_capacity() < S.sr_scratch_bytes(box, 3.0, n, True)
         dev = torch.device("cuda:0")
         x = torch.full((n,), 1.0, dtype=torch.float32, device=dev)
         out = tuple(torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
-        box = S.Box.make(160.0)
         with pytest.raises(S.SRError) as e:
             S.sr_force_static(ctx, x, x, x, x, box, 3.0, R_MAX, EPS, poly, out=out)
         assert "scratch" in str(e.value)
