@@ -254,7 +254,8 @@ __global__ __launch_bounds__(64) void k_force_persistent(Batch B, const int4 *__
                                                          const int *__restrict__ offsets,
                                                          const int *__restrict__ perm,
                                                          const int *__restrict__ mass_mixed,
-                                                         ForceParams fp, int *__restrict__ queue)
+                                                         ForceParams fp, int *__restrict__ queue,
+                                                         float4 *__restrict__ subsums)
 {
     __shared__ float4 tile[kTile];
     __shared__ Stencil st;
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(64) void k_force_persistent(Batch B, const int4 *__
         if (pos >= n)
             break;
         process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st,
-                     threadIdx.x, nullptr);
+                     threadIdx.x, subsums);
     }
 }
 
@@ -739,9 +740,7 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
     const int4 *items = order == 1 ? s.items_lpt : s.items;
     const int *n_items = s.bin.n_items;
     if (B.ntot > 0) {
-        // passes with sub-items need k_subsum after the pair loop: they take the
-        // grid below whatever the persistence setting
-        if (persistent && !s.part) {
+        if (persistent) {
             int dev_cus = 256;
             (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount,
                                         ctx->device);
@@ -753,7 +752,7 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
                 return rc;
             hipLaunchKernelGGL(k_force_persistent, dim3((unsigned)grid), dim3(64), 0, ctx->stream,
                                B, items, n_items, s.sorted, s.offsets, s.perm, s.bin.mass_mixed,
-                               fp, s.queue);
+                               fp, s.queue, s.part);
         } else {
             // with sub-items the item bound is loose: the grid covers the
             // chunk bound (at most kMaskedGrid workgroups in masked passes,
@@ -763,15 +762,16 @@ int force_enqueue(sr_ctx *ctx, const Batch &B, const ForceScratch &s, const Forc
                 grid = kMaskedGrid;
             hipLaunchKernelGGL(k_force, dim3(grid), dim3(64), 0, ctx->stream, B, items, n_items,
                                s.sorted, s.offsets, s.perm, s.bin.mass_mixed, fp, s.part);
-            if (s.part) {
-                if ((rc = sr_check_launch(ctx, "k_force")))
-                    return rc;
-                hipLaunchKernelGGL(k_subsum, dim3(kSubsumGrid), dim3(256), 0, ctx->stream, B,
-                                   s.heads, s.bin.n_heads, s.perm, s.part);
-            }
         }
         if ((rc = sr_check_launch(ctx, "k_force")))
             return rc;
+        // the sub-items' partial sums, added in order
+        if (s.part) {
+            hipLaunchKernelGGL(k_subsum, dim3(kSubsumGrid), dim3(256), 0, ctx->stream, B,
+                               s.heads, s.bin.n_heads, s.perm, s.part);
+            if ((rc = sr_check_launch(ctx, "k_subsum")))
+                return rc;
+        }
     }
     sr_timing_mark(ctx, rec, 2);
     if (mom) {
