@@ -420,7 +420,6 @@ __device__ __forceinline__ void merge_segment(const int *src, int P, int w, int 
 }
 
 constexpr int kSegGroup = 4;  // consecutive cells per wavefront
-constexpr int kFineChunk = 32;  // targets per item in cells flagged for finer items
 
 // Large cells are listed by size class, class c holding the cells of
 // kLargeCell 2^c + 1 .. kLargeCell 2^(c+1) particles (the last class: all
@@ -535,14 +534,11 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
         int q = mesh_chunks(len);
         // with an activity mask only the cell's na active particles (sorted
         // first) are targets: cells without one get no item, those flagged 2
-        // are cut into items of at most kFineChunk targets, marked kFineFlag
-        // for sub-items (k_cellid left the flags in chunk_count, the counts
-        // in tcount)
+        // are marked kFineFlag and cut by k_items (k_cellid left the flags in
+        // chunk_count, the counts in tcount)
         if (tcount) {
             const int f = chunk_count[c], na = tcount[c];
-            q = f == 0 ? 0
-                       : (f >= 2 ? ((na + kFineChunk - 1) / kFineChunk) | kFineFlag
-                                 : mesh_chunks(na));
+            q = f == 0 ? 0 : (f >= 2 ? kFineFlag : mesh_chunks(na));
         }
         chunk_count[c] = q;
     }

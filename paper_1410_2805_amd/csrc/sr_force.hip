@@ -358,11 +358,11 @@ __global__ __launch_bounds__(64) void k_pair_stats(Batch B, const int4 *__restri
 }
 
 // Work items of a block of 256 cells: each thread takes one cell's chunk
-// count and stencil size (chunks of cells flagged kFineFlag are cut into
-// sub-items by their source count; with split, the other chunks of boxes
-// that box_splits admits by their pair count; with target counts, a masked
-// pass, the chunks cover the cell's first tcount[c] slots, where its active
-// particles sit), the block
+// count and stencil size (cells flagged kFineFlag are chunked here: long
+// chunks cut into sub-items, short ones finer; with split, the chunks of
+// boxes that box_splits admits are cut into sub-items by their pair count;
+// with target counts, a masked pass, the chunks cover the cell's first
+// tcount[c] slots, where its active particles sit), the block
 // reserves its item range with one atomic on *n_items, then all threads
 // write the block's items, thread j the items j, j + 256, ... (the cell of an
 // item found by a binary search over the block's running item counts).  The
@@ -386,20 +386,27 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
     __shared__ long long s_src[256];
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int cc = c < B.ctot ? chunk_count[c] : 0;
-    const int q = cc & (kFineFlag - 1);
+    const bool fine = (cc & kFineFlag) != 0;
+    int q = cc & (kFineFlag - 1);
     int ns = 1, box = 0, b = 0, len = 0;
     long long src = 0;
-    if (q > 0) {
+    if (q > 0 || fine) {
         src = cell_stencil(B, offsets, c, &box, &b, &len);
         if (tcount)
             len = tcount[c];  // the active particles, sorted to the front of the cell
-        if (cc & kFineFlag) {
-            const long long k = (src + kSplitSources - 1) / kSplitSources;
-            ns = k < 1 ? 1 : (k > kMaxSrcSplit ? kMaxSrcSplit : (int)k);
+        long long k = 1;
+        if (fine) {
+            // long chunks (dense cells): whole chunks cut into sub-items by
+            // their pair count; short ones: chunks of at most kFineChunk
+            // targets, so that passes over few cells still have many items
+            const int qm = mesh_chunks(len);
+            const long long pm = src * ((len + qm - 1) / qm);
+            q = pm > kSplitPairs ? qm : (len + kFineChunk - 1) / kFineChunk;
+            k = pm > kSplitPairs ? (pm + kSplitPairs - 1) / kSplitPairs : 1;
         } else if (split && box_splits(box_at(B, box).n)) {
-            const long long k = (src * ((len + q - 1) / q) + kSplitPairs - 1) / kSplitPairs;
-            ns = k < 1 ? 1 : (k > kMaxSrcSplit ? kMaxSrcSplit : (int)k);
+            k = (src * ((len + q - 1) / q) + kSplitPairs - 1) / kSplitPairs;
         }
+        ns = k < 1 ? 1 : (k > kMaxSrcSplit ? kMaxSrcSplit : (int)k);
     }
     const int m = q * ns;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

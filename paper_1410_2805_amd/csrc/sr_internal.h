@@ -399,13 +399,14 @@ __device__ __forceinline__ int mesh_chunks(int n)
 // q, (k + 1) n / q); a chunk is one item, or ns sub-items that take
 // consecutive parts [sk T / ns, (sk + 1) T / ns) of the T stencil sources,
 // so that the pairs of a dense cell spread over more wavefronts and no
-// single wavefront holds up the end of the pass: chunks of cells flagged for
-// finer items (multilevel passes over few dense cells) by their source
-// count, other chunks by their pair count.  A sub-item leaves partial sums,
-// which a second pass adds in sub-item order.
+// single wavefront holds up the end of the pass (a chunk of P target-source
+// pairs takes ceil(P / kSplitPairs) sub-items, at most kMaxSrcSplit).  Cells
+// flagged for finer items (multilevel passes) are cut so in any box, and
+// their short chunks into chunks of at most kFineChunk targets instead.  A
+// sub-item leaves partial sums, which a second pass adds in sub-item order.
 constexpr int kMaxSrcSplit = 8;       // sub-items per chunk at most
-constexpr int kSplitSources = 4096;   // stencil sources per sub-item, about (finer items)
-constexpr long long kSplitPairs = 1 << 20;  // target-source pairs per sub-item, about (other chunks)
+constexpr int kFineChunk = 32;        // targets per item of short chunks in flagged cells
+constexpr long long kSplitPairs = 1 << 20;  // target-source pairs per sub-item, about
 constexpr int64_t kSplitMaxN = 1 << 22;     // boxes of at most this many particles cut other chunks
 
 // Whether the chunks of a box of n particles (other than those of cells
