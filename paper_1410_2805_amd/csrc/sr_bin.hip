@@ -510,8 +510,9 @@ __device__ void sort_cell(int cell, int b, int len, int *__restrict__ perm, int 
 // One wavefront per group of kSegGroup consecutive cells.  When the group
 // holds at most 64 particles, each lane takes one slot and ranks its index
 // among the smaller indices of the same cell (one pass for the whole group);
-// otherwise the cells are sorted one after the other.  With chunk_count, the
-// pass also counts the force work items of each cell (mesh_chunks_for).
+// otherwise the cells are sorted one after the other.  With an activity mask
+// (chunk_count and tcount), the pass also counts the force work items of
+// each cell (mesh_chunks_for).
 // Indices are compared as the signed keys k_scatter wrote.
 __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restrict__ offsets,
                                                     int *__restrict__ perm,
@@ -528,19 +529,14 @@ __global__ __launch_bounds__(kBlock) void k_segsort(Batch B, const int *__restri
     if (c0 >= B.ctot)
         return;
     const int nc = B.ctot - c0 < kSegGroup ? B.ctot - c0 : kSegGroup;
-    if (chunk_count && lane < nc) {
-        const int c = c0 + lane;
-        const int len = offsets[c + 1] - offsets[c];
-        int q = mesh_chunks(len);
+    if (chunk_count && tcount && lane < nc) {
         // with an activity mask only the cell's na active particles (sorted
         // first) are targets: cells without one get no item, those flagged 2
         // are marked kFineFlag and cut by k_items (k_cellid left the flags in
         // chunk_count, the counts in tcount)
-        if (tcount) {
-            const int f = chunk_count[c], na = tcount[c];
-            q = f == 0 ? 0 : (f >= 2 ? kFineFlag : mesh_chunks(na));
-        }
-        chunk_count[c] = q;
+        const int c = c0 + lane;
+        const int f = chunk_count[c], na = tcount[c];
+        chunk_count[c] = f == 0 ? 0 : (f >= 2 ? kFineFlag : mesh_chunks(na));
     }
     int bounds[kSegGroup + 1];
 #pragma unroll
@@ -790,6 +786,161 @@ __global__ __launch_bounds__(kLargeBlock) void k_segsort_large(Batch B,
     }
 }
 
+// ---- Binning by a stable LSD radix sort (passes of at least kRadixMinN
+// particles without an activity mask).  Scattered input gives every block of
+// the histogram pass above hundreds of distinct cells, and its global return
+// atomics (about one per particle) then bound the binning; a radix sort
+// needs none.  Each pass sorts the (cell id, index) pairs stably by the next
+// kRadixBits bits of the id: per tile a digit histogram, one scan over the
+// digit-major (digit, tile) matrix, then each tile writes its elements to
+// their digit's range in index order.  Starting from the indices in order,
+// the result is the stable sort by cell, i.e. exactly the permutation of the
+// counting sort with per-cell index sorts.
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixPer = 16;                   // elements per thread and tile
+constexpr int kRadixTile = kBlock * kRadixPer;  // 4096 elements per tile
+constexpr int64_t kRadixMinN = 1 << 22;         // passes this large bin by radix sort
+static_assert(kBlock == kRadixBins, "one thread per digit");
+
+// The lanes of the wavefront whose digit equals this lane's (valid lanes only).
+__device__ __forceinline__ unsigned long long digit_peers(unsigned d, bool valid)
+{
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const unsigned long long one = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? one : ~one;
+    }
+    return m;
+}
+
+// Cell ids only (the radix path's keys), with the status word.
+__global__ __launch_bounds__(kBlock) void k_cellkey(Batch B, unsigned *__restrict__ keys,
+                                                    int *__restrict__ status)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < B.ntot)
+        keys[i] = (unsigned)particle_cell(B, i, status);
+}
+
+// hist[d * ntiles + t] = number of elements of tile t whose digit is d.
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const unsigned *__restrict__ keys, int n,
+                                                       int shift, int ntiles,
+                                                       int *__restrict__ hist)
+{
+    __shared__ int cnt[kRadixBins];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int base = blockIdx.x * kRadixTile;
+    for (int r = 0; r < kRadixPer; ++r) {
+        const int e = base + r * kBlock + threadIdx.x;
+        const bool valid = e < n;
+        const unsigned d = valid ? (keys[e] >> shift) & (kRadixBins - 1) : 0u;
+        const unsigned long long m = digit_peers(d, valid);
+        // the lowest lane of each digit adds its group's count
+        if (valid && (m & ((1ull << lane) - 1ull)) == 0ull)
+            atomicAdd(&cnt[d], __popcll(m));
+    }
+    __syncthreads();
+    hist[threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// One pass's scatter, staged through LDS.  Element e of tile t (e = t
+// kRadixTile + r kBlock + thread) takes the slot of its digit's range within
+// the tile (the exclusive scan of the tile's digit counts) plus the number of
+// same-digit elements before it in the tile: those of earlier rounds (run),
+// of lower wavefronts in this round (wc) and of lower lanes (a ballot match).
+// The tile, so sorted in LDS, is then written out in slot order: each
+// digit's elements land as one run at the tile's scanned global offset
+// (hist, digit-major: its next entry minus this one is the tile's count).
+// vals_in NULL: the values are the indices; inv, when given, receives
+// inv[value] = position.
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const unsigned *__restrict__ keys_in, const int *__restrict__ vals_in, int n, int shift,
+    int ntiles, const int *__restrict__ hist, unsigned *__restrict__ keys_out,
+    int *__restrict__ vals_out, int *__restrict__ inv)
+{
+    __shared__ unsigned lkey[kRadixTile];
+    __shared__ int lval[kRadixTile];
+    __shared__ int run[kRadixBins];    // next tile slot of each digit
+    __shared__ int lbase[kRadixBins];  // first tile slot of each digit
+    __shared__ int gbase[kRadixBins];  // first global position of each digit's run
+    __shared__ int wc[kBlock / 64][kRadixBins];
+    __shared__ int sh[kBlock / 64 + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    {
+        const int h = threadIdx.x * ntiles + blockIdx.x;
+        const int g = hist[h];
+        int total;
+        const int ex = block_exclusive_scan(hist[h + 1] - g, sh, &total);
+        gbase[threadIdx.x] = g;
+        lbase[threadIdx.x] = ex;
+        run[threadIdx.x] = ex;
+    }
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w)
+        wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kRadixTile;
+    for (int r = 0; r < kRadixPer; ++r) {
+        const int e = base + r * kBlock + threadIdx.x;
+        const bool valid = e < n;
+        const unsigned key = valid ? keys_in[e] : 0u;
+        const int val = valid ? (vals_in ? vals_in[e] : e) : 0;
+        const unsigned d = (key >> shift) & (kRadixBins - 1);
+        const unsigned long long m = digit_peers(d, valid);
+        const int below = __popcll(m & ((1ull << lane) - 1ull));
+        if (valid && below == 0)
+            wc[wid][d] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int pos = run[d] + below;
+            for (int w = 0; w < wid; ++w)
+                pos += wc[w][d];
+            lkey[pos] = key;
+            lval[pos] = val;
+        }
+        __syncthreads();
+        // digit threadIdx.x: advance its running slot, clear its counts
+        int add = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            add += wc[w][threadIdx.x];
+            wc[w][threadIdx.x] = 0;
+        }
+        run[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const int cnt = n - base < kRadixTile ? n - base : kRadixTile;
+    for (int j = threadIdx.x; j < cnt; j += kBlock) {
+        const unsigned key = lkey[j];
+        const int val = lval[j];
+        const unsigned d = (key >> shift) & (kRadixBins - 1);
+        const int pos = gbase[d] + (j - lbase[d]);
+        keys_out[pos] = key;
+        vals_out[pos] = val;
+        if (inv)
+            inv[val] = pos;
+    }
+}
+
+// Cell offsets from the sorted ids: slot k starts the cells c with
+// keys[k - 1] < c <= keys[k] (k = n: every cell after the last id, and the
+// end offset).
+__global__ __launch_bounds__(kBlock) void k_key_offsets(const unsigned *__restrict__ keys, int n,
+                                                        int ctot, int *__restrict__ offsets)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k > n)
+        return;
+    const int lo = k == 0 ? 0 : (int)keys[k - 1] + 1;
+    const int hi = k == n ? ctot : (int)keys[k];
+    for (int c = lo; c <= hi; ++c)
+        offsets[c] = k;
+}
+
 inline unsigned blocks_for(int64_t n, int per)
 {
     return (unsigned)((n + per - 1) / per);
@@ -861,6 +1012,56 @@ void bin_layout(Bump &b, int64_t ntot, int64_t ctot, int nb, BinScratch &s)
     s.lpt = b.take<int>(64);
     s.n_items = b.take<int>(1);
     s.n_heads = b.take<int>(1);
+    s.vtmp = s.ktmp = s.hist = s.hist_part = nullptr;
+    if (ntot >= kRadixMinN) {
+        const int64_t m = (int64_t)kRadixBins * ((ntot + kRadixTile - 1) / kRadixTile);
+        s.vtmp = b.take<int>(nn);
+        s.ktmp = b.take<int>(nn);
+        s.hist = b.take<int>((size_t)m + 1);
+        scan_layout(b, (int)m, &s.hist_part);
+    }
+}
+
+// The radix path of bin_enqueue (offsets, perm and the inverse).  The ids
+// stay in cid in input order, as the counting sort leaves them (the tree
+// pass reads them); the passes' keys alternate between tmp and ktmp, their
+// indices between vtmp and perm.
+static int radix_bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets,
+                             int *perm, int *inv)
+{
+    const int n = B.ntot;
+    const int ntiles = (n + kRadixTile - 1) / kRadixTile;
+    const int m = kRadixBins * ntiles;
+    unsigned *ids = reinterpret_cast<unsigned *>(s.cid);
+    unsigned *kb[2] = {reinterpret_cast<unsigned *>(s.ktmp), reinterpret_cast<unsigned *>(s.tmp)};
+    hipLaunchKernelGGL(k_cellkey, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, B,
+                       ids, ctx->status);
+    int rc = sr_check_launch(ctx, "k_cellkey");
+    if (rc)
+        return rc;
+    const unsigned maxkey = (unsigned)(B.ctot > 1 ? B.ctot - 1 : 1);
+    const int bits = 32 - __builtin_clz(maxkey);
+    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    for (int p = 0; p < passes; ++p) {
+        // the last pass writes the indices to perm
+        const int *vin = p == 0 ? nullptr : ((passes - p) % 2 == 0 ? perm : s.vtmp);
+        int *vout = (passes - p - 1) % 2 == 0 ? perm : s.vtmp;
+        // pass p reads the keys pass p - 1 wrote (the ids for p = 0), writes kb[(p + 1) & 1]
+        const unsigned *kin = p == 0 ? ids : kb[p & 1];
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), 0, ctx->stream, kin, n,
+                           p * kRadixBits, ntiles, s.hist);
+        if ((rc = sr_check_launch(ctx, "k_radix_hist")) ||
+            (rc = scan_enqueue(ctx, s.hist, m, s.hist_part, s.hist, s.scan_flag)))
+            return rc;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kBlock), 0, ctx->stream, kin,
+                           vin, n, p * kRadixBits, ntiles, s.hist, kb[(p + 1) & 1], vout,
+                           p == passes - 1 ? inv : nullptr);
+        if ((rc = sr_check_launch(ctx, "k_radix_scatter")))
+            return rc;
+    }
+    hipLaunchKernelGGL(k_key_offsets, dim3(blocks_for((int64_t)n + 1, kBlock)), dim3(kBlock), 0,
+                       ctx->stream, kb[passes & 1], n, B.ctot, offsets);
+    return sr_check_launch(ctx, "k_key_offsets");
 }
 
 // Enqueue the whole binning pass.  sorted and chunk_count may be NULL (then
@@ -899,6 +1100,20 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
     if (masked && ((rc = fill_enqueue(ctx, chunk_count, 0, B.ctot)) ||
                    (rc = fill_enqueue(ctx, tcount, 0, B.ctot))))
         return rc;
+    // the arrival ranks are not needed once the cells are sorted: their
+    // buffer takes the inverse permutation
+    int *inv = sorted ? s.slot : nullptr;
+    if (!masked && s.vtmp && n >= kRadixMinN) {
+        if ((rc = radix_bin_enqueue(ctx, B, s, offsets, perm, inv)))
+            return rc;
+        if (sorted) {
+            hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0,
+                               ctx->stream, B, inv, sorted, s.mass_mixed);
+            if ((rc = sr_check_launch(ctx, "k_gather")))
+                return rc;
+        }
+        return SR_OK;
+    }
     if (n > 0) {
         if (masked)
             hipLaunchKernelGGL(k_cellid<true>, dim3(blocks_for(n, kCellidBlock)), dim3(kBlock), 0,
@@ -919,11 +1134,9 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
         if ((rc = sr_check_launch(ctx, "k_scatter")))
             return rc;
     }
-    // the arrival ranks are no longer needed: reuse them as the inverse
-    int *inv = sorted ? s.slot : nullptr;
     hipLaunchKernelGGL(k_segsort, dim3(blocks_for(B.ctot, kBlock / 64 * kSegGroup)), dim3(kBlock), 0,
                        ctx->stream, B, offsets, perm, s.large_list, s.large_count, inv,
-                       chunk_count, masked ? tcount : nullptr);
+                       masked ? chunk_count : nullptr, masked ? tcount : nullptr);
     if ((rc = sr_check_launch(ctx, "k_segsort")))
         return rc;
     if (n > kLargeCell) {

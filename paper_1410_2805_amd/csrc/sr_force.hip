@@ -385,7 +385,10 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
     __shared__ int s_q[256], s_ns[256], s_b[256], s_len[256], s_box[256];
     __shared__ long long s_src[256];
     const int c = blockIdx.x * 256 + threadIdx.x;
-    const int cc = c < B.ctot ? chunk_count[c] : 0;
+    // masked passes: the counts binning left; otherwise the cell's chunks
+    const int cc = c >= B.ctot ? 0
+                   : tcount    ? chunk_count[c]
+                               : mesh_chunks(offsets[c + 1] - offsets[c]);
     const bool fine = (cc & kFineFlag) != 0;
     int q = cc & (kFineFlag - 1);
     int ns = 1, box = 0, b = 0, len = 0;

@@ -185,6 +185,11 @@ struct BinScratch {
     int *lpt;         // [64] key totals and cursors of the longest-first item order
     int *n_items;     // [1] force work items appended by k_items
     int *n_heads;     // [1] chunks cut into sub-items, appended by k_items
+    // radix-sort binning (passes of many particles; null otherwise)
+    int *vtmp;        // [ntot] index ping-pong buffer
+    int *ktmp;        // [ntot] key ping-pong buffer (with tmp; cid keeps the ids)
+    int *hist;        // [digits * tiles + 1] per-tile digit counts, scanned in place
+    int *hist_part;   // scan partials of hist
 };
 
 // Up to seven int buffers zeroed by one kernel launch.

@@ -122,10 +122,37 @@ def test_zeldovich_128(sr, ctx):
 
 
 def test_nfw_256(sr, ctx):
+    """The 256^3 clustered share (radix path: 2^22 particles or more)."""
     p = W.config("nfw256")
     off, perm, o_off, o_perm = _bin_both(sr, ctx, p.x, p.y, p.z, 256.0, 3.0, periodic=False)
     _assert_same(off, perm, o_off, o_perm)
-    assert np.diff(off).max() > 1025  # the large-cell path was exercised
+    assert np.diff(off).max() > 1025  # cells of more than 1024 particles
+
+
+@pytest.mark.parametrize("case", ["uniform", "one_cell", "cell_order", "two_cells"])
+def test_radix_path(sr, ctx, case):
+    """Passes of at least 2^22 particles bin by a stable radix sort of the
+    cell ids (three 8-bit passes for 10^6 cells): bit-exact against the
+    oracle's counting sort with a ragged count (2^22 + 123), many empty
+    cells, every particle in one cell, input already in cell order, and two
+    cells of interleaved particles (every digit pass sees one or two
+    digits)."""
+    n = (1 << 22) + 123
+    L = 300.0
+    rng = np.random.default_rng(len(case))
+    if case == "one_cell":
+        v = rng.random((n, 3)) * 2.9
+    elif case == "two_cells":
+        v = rng.random((n, 3)) * 2.9
+        v[1::2, 0] += 3.0 * 77
+    else:
+        v = np.minimum(rng.random((n, 3)) * L, np.float32(299.99))
+    x, y, z = (np.ascontiguousarray(v[:, k], dtype=np.float32) for k in range(3))
+    if case == "cell_order":
+        _, o_perm, _ = O.bin(x, y, z, L, 3.0)
+        x, y, z = x[o_perm], y[o_perm], z[o_perm]
+    print("case:", case, n, flush=True)
+    _assert_same(*_bin_both(sr, ctx, x, y, z, L, 3.0))
 
 
 def test_invalid_args(sr, ctx):
