@@ -384,6 +384,7 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
     __shared__ int s_end[256];  // the block's items up to and including each cell
     __shared__ int s_q[256], s_ns[256], s_b[256], s_len[256], s_box[256];
     __shared__ long long s_src[256];
+    __shared__ bool s_mesh[256];  // chunks laid out as mesh_chunks lays them out, or equal
     const int c = blockIdx.x * 256 + threadIdx.x;
     // masked passes: the counts binning left; otherwise the cell's chunks
     const int cc = c >= B.ctot ? 0
@@ -392,6 +393,7 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
     const bool fine = (cc & kFineFlag) != 0;
     int q = cc & (kFineFlag - 1);
     int ns = 1, box = 0, b = 0, len = 0;
+    bool mesh = true;
     long long src = 0;
     if (q > 0 || fine) {
         src = cell_stencil(B, offsets, c, &box, &b, &len);
@@ -401,11 +403,15 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
         if (fine) {
             // long chunks (dense cells): whole chunks cut into sub-items by
             // their pair count; short ones: chunks of at most kFineChunk
-            // targets, so that passes over few cells still have many items
+            // targets cut by their source count, so that passes over few
+            // cells still have many items
             const int qm = mesh_chunks(len);
             const long long pm = src * ((len + qm - 1) / qm);
-            q = pm > kSplitPairs ? qm : (len + kFineChunk - 1) / kFineChunk;
-            k = pm > kSplitPairs ? (pm + kSplitPairs - 1) / kSplitPairs : 1;
+            const bool whole = pm > kSplitPairs;
+            mesh = whole;
+            q = whole ? qm : (len + kFineChunk - 1) / kFineChunk;
+            k = whole ? (pm + kSplitPairs - 1) / kSplitPairs
+                      : (src + kFineSources - 1) / kFineSources;
         } else if (split && box_splits(box_at(B, box).n)) {
             k = (src * ((len + q - 1) / q) + kSplitPairs - 1) / kSplitPairs;
         }
@@ -431,6 +437,7 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
     s_len[threadIdx.x] = len;
     s_box[threadIdx.x] = box;
     s_src[threadIdx.x] = src;
+    s_mesh[threadIdx.x] = mesh;
     __syncthreads();
     const int T = s_end[255];
     for (int j = threadIdx.x; j < T; j += 256) {
@@ -446,8 +453,8 @@ __global__ __launch_bounds__(256) void k_items(Batch B, const int *__restrict__ 
         const int r = j - (s_end[lo] - qq * nn);
         const int k = r / nn;
         int bucket;
-        const int4 it = cell_item(blockIdx.x * 256 + lo, s_box[lo], s_b[lo], s_len[lo], qq, k,
-                                  nn, r - k * nn, s_src[lo], &bucket);
+        const int4 it = cell_item(blockIdx.x * 256 + lo, s_box[lo], s_b[lo], s_len[lo], qq,
+                                  s_mesh[lo], k, nn, r - k * nn, s_src[lo], &bucket);
         items[base + j] = it;
         item_cost[base + j] = bucket;
         if (nn > 1 && r == k * nn)

@@ -417,13 +417,13 @@ __device__ __forceinline__ int mesh_chunks(int n)
     return full + kChunkTab.mesh[n - full * kChunk2];
 }
 
-// Targets [*lo, *hi) of chunk k of q of a cell of len targets: the layout
-// of mesh_chunks when q is its count, else q nearly equal parts [k len / q,
-// (k + 1) len / q).
-__device__ __forceinline__ void chunk_range(int len, int q, int k, int *lo, int *hi)
+// Targets [*lo, *hi) of chunk k of q of a cell of len targets: with mesh,
+// the layout of mesh_chunks (q its count), else q nearly equal parts [k len /
+// q, (k + 1) len / q).
+__device__ __forceinline__ void chunk_range(int len, int q, int k, bool mesh, int *lo, int *hi)
 {
     int base = 0;
-    if (len > 4 * kChunk && q == mesh_chunks(len)) {
+    if (mesh && len > 4 * kChunk) {
         const int full = mesh_full_chunks(len);
         if (k < full) {
             *lo = k * kChunk2;
@@ -452,6 +452,7 @@ __device__ __forceinline__ void chunk_range(int len, int q, int k, int *lo, int 
 // sub-item leaves partial sums, which a second pass adds in sub-item order.
 constexpr int kMaxSrcSplit = 8;       // sub-items per chunk at most
 constexpr int kFineChunk = 32;        // targets per item of short chunks in flagged cells
+constexpr int kFineSources = 4096;    // stencil sources per sub-item of those chunks, about
 constexpr long long kSplitPairs = 1 << 20;  // target-source pairs per sub-item, about
 constexpr int64_t kSplitMaxN = 1 << 22;     // boxes of at most this many particles cut other chunks
 
@@ -518,14 +519,15 @@ __device__ inline long long cell_stencil(const Batch &B, const int *__restrict__
 }
 
 // Sub-item sk of chunk k of a cell (first sorted slot b, len targets, q
-// chunks, ns sub-items per chunk, src stencil sources), shaped by item_shape;
+// chunks laid out as mesh_chunks lays them out (mesh) or equal, ns sub-items
+// per chunk, src stencil sources), shaped by item_shape;
 // *bucket is floor(log2(cost)), cost = (the sub-item's sources) x (the
 // shape's cost per source) + 64 (wavefront iterations plus overhead).
-__device__ inline int4 cell_item(int c, int box, int b, int len, int q, int k, int ns, int sk,
-                                 long long src, int *bucket)
+__device__ inline int4 cell_item(int c, int box, int b, int len, int q, bool mesh, int k, int ns,
+                                 int sk, long long src, int *bucket)
 {
     int lo, hi;
-    chunk_range(len, q, k, &lo, &hi);
+    chunk_range(len, q, k, mesh, &lo, &hi);
     int tpl, S;
     const float pass = item_shape(hi - lo, &tpl, &S);
     const long long cost = (long long)((float)(src / ns) * pass) + 64;
