@@ -205,7 +205,7 @@ struct ForceScratch {
     int *offsets;     // [ctot + 1]
     int *perm;        // [ntot]
     float4 *sorted;   // [ntot] (x, y, z, m) in cell order
-    int *chunk_count; // [ctot] work items per cell (activity flags first, when masked)
+    int *chunk_count; // [ctot] masked passes: activity flags, then chunks per cell
     int4 *items;      // [item bound] in cell order
     int *item_cost;   // [item bound] cost bucket of each item
     int4 *items_lpt;  // [item bound] items by decreasing cost bucket
@@ -441,8 +441,8 @@ __device__ __forceinline__ void chunk_range(int len, int q, int k, bool mesh, in
     *hi = base + (small ? (k + 1) * len / q : (int)((long long)(k + 1) * len / q));
 }
 
-// Work items.  A cell of n targets is cut into q nearly equal chunks [k n /
-// q, (k + 1) n / q); a chunk is one item, or ns sub-items that take
+// Work items.  A cell's targets are cut into q chunks (chunk_range); a chunk
+// is one item, or ns sub-items that take
 // consecutive parts [sk T / ns, (sk + 1) T / ns) of the T stencil sources,
 // so that the pairs of a dense cell spread over more wavefronts and no
 // single wavefront holds up the end of the pass (a chunk of P target-source
