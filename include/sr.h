@@ -118,7 +118,8 @@ int sr_grid_dims(const sr_box *box, double cell, int32_t dims[3], int64_t *n_cel
  * particle (about 210 bytes per particle in all; about 41 beyond). */
 int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force, size_t *bytes);
 
-/* Chaining-mesh binning (a stable counting sort by cell).
+/* Chaining-mesh binning (a stable sort by cell: a counting sort, or for
+ * n >= 2^22 an LSD radix sort of the cell ids, with the same result).
  *   x, y, z      : device float32[n], 0 <= coordinate < len.
  *   n            : 0 <= n <= 2^31 - 1.
  *   cell         : requested cell width (see sr_grid_dims).
