@@ -926,19 +926,23 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     }
 }
 
-// Cell offsets from the sorted ids: slot k starts the cells c with
-// keys[k - 1] < c <= keys[k] (k = n: every cell after the last id, and the
-// end offset).
+// Cell offsets from the sorted ids: offsets[c] = the first slot whose id is
+// at least c (n if none), by binary search, one thread per entry c <= ctot.
 __global__ __launch_bounds__(kBlock) void k_key_offsets(const unsigned *__restrict__ keys, int n,
                                                         int ctot, int *__restrict__ offsets)
 {
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k > n)
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c > ctot)
         return;
-    const int lo = k == 0 ? 0 : (int)keys[k - 1] + 1;
-    const int hi = k == n ? ctot : (int)keys[k];
-    for (int c = lo; c <= hi; ++c)
-        offsets[c] = k;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < (unsigned)c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    offsets[c] = lo;
 }
 
 inline unsigned blocks_for(int64_t n, int per)
@@ -1059,8 +1063,8 @@ static int radix_bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, i
         if ((rc = sr_check_launch(ctx, "k_radix_scatter")))
             return rc;
     }
-    hipLaunchKernelGGL(k_key_offsets, dim3(blocks_for((int64_t)n + 1, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, kb[passes & 1], n, B.ctot, offsets);
+    hipLaunchKernelGGL(k_key_offsets, dim3(blocks_for((int64_t)B.ctot + 1, kBlock)), dim3(kBlock),
+                       0, ctx->stream, kb[passes & 1], n, B.ctot, offsets);
     return sr_check_launch(ctx, "k_key_offsets");
 }
 
