@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_momentum_partial(Batch B, double *__res
         sh[k][threadIdx.x] = s[k];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             for (int k = 0; k < 3; ++k)
                 sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
         __syncthreads();
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(256) void k_momentum_final(const double *__restrict
     }
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             for (int k = 0; k < 3; ++k)
                 sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
         __syncthreads();

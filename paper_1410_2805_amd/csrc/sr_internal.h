@@ -361,7 +361,7 @@ __host__ __device__ constexpr inline int mesh_chunks_for(int n)
     for (int q = q0; q <= qmax; ++q) {
         float c = 0.05f * (float)q;
         for (int k = 0; k < q; ++k) {
-            int tpl, S;
+            int tpl = 0, S = 0;
             c += item_shape((k + 1) * n / q - k * n / q, &tpl, &S);
         }
         if (c < best) {
