@@ -19,7 +19,10 @@
 //              permutation and, for the force pass, the work items per cell.
 //   k_gather   the sorted float4 (x, y, z, m) copy, through the inverse.
 // All kernels work on a batch of boxes whose particles and cells are numbered
-// consecutively; one box is a batch of one.
+// consecutively; one box is a batch of one.  A pass with an activity mask
+// bins only the cells whose stencil reaches a cell holding an active particle
+// (k_relevant): every source of every target, in the same order, with the
+// other cells left empty.
 #include <climits>
 
 #include "sr_internal.h"
@@ -310,8 +313,48 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int *__restrict__ cid,
                                                     int *__restrict__ perm)
 {
     int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n)
-        perm[offsets[cid[i]] + slot[i]] = active && active[i] ? (i | INT_MIN) : i;
+    if (i >= n)
+        return;
+    const int c = cid[i];
+    const int o = offsets[c];
+    // masked: the particles of cells left empty (k_relevant) take no slot
+    if (active && offsets[c + 1] == o)
+        return;
+    perm[o + slot[i]] = active && active[i] ? (i | INT_MIN) : i;
+}
+
+// Masked passes: a cell is binned when its stencil (x +-hx, y and z +-1,
+// periodic: masked passes run in split coordinates) reaches a cell flagged
+// active (flag[c] > 0, left by k_cellid); the counts of the others are set to
+// zero before the scan, so those cells stay empty.  The cells a target's
+// stencil reaches are all binned, in the order a full pass gives them, so the
+// sums are those of the full pass.
+__global__ __launch_bounds__(kBlock) void k_relevant(Geom g, const int *__restrict__ flag,
+                                                     int *__restrict__ count)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncell || count[c] == 0)
+        return;
+    const int cz = div_by(c, g.div_m[0], g.div_s[0]);
+    const int rem = c - cz * g.nc[0] * g.nc[1];
+    const int cy = div_by(rem, g.div_m[1], g.div_s[1]);
+    const int cx = rem - cy * g.nc[0];
+    for (int dz = -1; dz <= 1; ++dz) {
+        int nz = cz + dz;
+        nz = nz < 0 ? nz + g.nc[2] : (nz >= g.nc[2] ? nz - g.nc[2] : nz);
+        for (int dy = -1; dy <= 1; ++dy) {
+            int ny = cy + dy;
+            ny = ny < 0 ? ny + g.nc[1] : (ny >= g.nc[1] ? ny - g.nc[1] : ny);
+            const int row = g.nc[0] * (ny + g.nc[1] * nz);
+            for (int dx = -g.hx; dx <= g.hx; ++dx) {
+                int nx = cx + dx;
+                nx = nx < 0 ? nx + g.nc[0] : (nx >= g.nc[0] ? nx - g.nc[0] : nx);
+                if (flag[row + nx] > 0)
+                    return;
+            }
+        }
+    }
+    count[c] = 0;
 }
 
 __device__ __forceinline__ int bitonic64(int v, int lane)
@@ -351,7 +394,9 @@ __device__ __forceinline__ float4 gather_one(const BoxDesc &d, int v)
 // neighbours together.  Also flags boxes whose masses are not all equal.
 __global__ __launch_bounds__(kBlock) void k_gather(Batch B, const int *__restrict__ inv,
                                                    float4 *__restrict__ sorted,
-                                                   int *__restrict__ mass_mixed)
+                                                   int *__restrict__ mass_mixed,
+                                                   const int *__restrict__ cid,
+                                                   const int *__restrict__ offsets)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     bool mixed = false;
@@ -360,7 +405,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(Batch B, const int *__restric
         box = find_box(B.pstart, B.nb, i);
         const BoxDesc &d = box_at(B, box);
         const float4 q = gather_one(d, i);
-        sorted[inv[i]] = q;
+        // with cid (masked passes) the particles of empty cells have no slot;
+        // every mass still decides mass_mixed, as in a full pass
+        if (!cid || offsets[cid[i] + 1] != offsets[cid[i]])
+            sorted[inv[i]] = q;
         mixed = q.w != d.m[0];
     }
     // one atomic per wavefront for the lanes that share the lowest flagged
@@ -1112,7 +1160,7 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
             return rc;
         if (sorted) {
             hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0,
-                               ctx->stream, B, inv, sorted, s.mass_mixed);
+                               ctx->stream, B, inv, sorted, s.mass_mixed, nullptr, nullptr);
             if ((rc = sr_check_launch(ctx, "k_gather")))
                 return rc;
         }
@@ -1129,6 +1177,12 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
                                nullptr);
         if ((rc = sr_check_launch(ctx, "k_cellid")))
             return rc;
+        if (masked) {
+            hipLaunchKernelGGL(k_relevant, dim3(blocks_for(B.ctot, kBlock)), dim3(kBlock), 0,
+                               ctx->stream, B.one.g, chunk_count, s.count);
+            if ((rc = sr_check_launch(ctx, "k_relevant")))
+                return rc;
+        }
     }
     if ((rc = scan_enqueue(ctx, s.count, B.ctot, s.scan_part, offsets, s.scan_flag)))
         return rc;
@@ -1161,7 +1215,8 @@ int bin_enqueue(sr_ctx *ctx, const Batch &B, const BinScratch &s, int *offsets, 
     }
     if (sorted && n > 0) {
         hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, ctx->stream,
-                           B, inv, sorted, s.mass_mixed);
+                           B, inv, sorted, s.mass_mixed, masked ? s.cid : nullptr,
+                           masked ? offsets : nullptr);
         if ((rc = sr_check_launch(ctx, "k_gather")))
             return rc;
     }
