@@ -19,7 +19,10 @@
 //              permutation and, for the force pass, the work items per cell.
 //   k_gather   the sorted float4 (x, y, z, m) copy, through the inverse.
 // All kernels work on a batch of boxes whose particles and cells are numbered
-// consecutively; one box is a batch of one.  A pass with an activity mask
+// consecutively; one box is a batch of one.  Passes of 2^22 particles or
+// more without an activity mask take a stable LSD radix sort of the cell ids
+// instead (k_cellkey, k_radix_*, k_key_offsets): the same offsets and
+// permutation without the histogram's global atomics.  A pass with an activity mask
 // bins only the cells whose stencil reaches a cell holding an active particle
 // (k_relevant): every source of every target, in the same order, with the
 // other cells left empty.

@@ -1,11 +1,13 @@
 // Short-range particle-particle force on gfx950 (Eq. (force), Sec. 3.1).
 //
 // After binning (sr_bin.hip) the particles sit cell by cell in a float4
-// (x, y, z, m) copy.  Each force work item is one cell's chunk of at most 64
-// targets.  One wavefront owns an item:
+// (x, y, z, m) copy.  Each force work item is one cell's chunk of at most 128
+// targets, or a sub-item taking a consecutive part of that chunk's stencil
+// sources.  One wavefront owns an item:
 //   - the 27 neighbour cells are 9 rows of 3 cells that are contiguous in the
 //     sorted order, so the source list is at most 18 contiguous pieces (a row
-//     splits in two where it wraps around a periodic face);
+//     splits in two where it wraps around a periodic face; in split
+//     coordinates each neighbour cell is a piece of its own);
 //   - sources are staged through LDS in tiles of kTile with their periodic
 //     image shift applied, then read back by broadcast;
 //   - when a cell holds few targets the 64 lanes are split into S groups that
@@ -24,8 +26,10 @@
 // Everything runs on a batch of boxes (one box = a batch of one): a work item
 // carries its box, whose geometry, inputs and outputs it reads from the
 // batch descriptor.  Items may be ordered by decreasing cost bucket (longest
-// first) and are either one workgroup each or pulled from a counter by
-// persistent workgroups.
+// first) and are either one workgroup each (a workgroup also takes positions
+// + k gridDim when sub-items outnumber the grid) or pulled from a counter by
+// persistent workgroups; the sub-items' partial sums are then added by
+// k_subsum.
 #include <climits>
 #include <cmath>
 
