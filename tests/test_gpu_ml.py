@@ -112,6 +112,35 @@ def test_multilevel_step_matches_oracle(sr, ctx, d, lmin, lmax):
     assert np.abs(dx).max() <= 2e-5 * dt * vs + 1e-6
 
 
+@pytest.mark.parametrize("xsplit", [2, 3])
+def test_multilevel_x_subcells_match_oracle(sr, ctx, xsplit):
+    """Masked passes on x sub-cells: a stencil spans +-xsplit sub-cells in x,
+    so the cells binned around each active one (and the targets' stencils)
+    span that far too; the step still follows the FP64 oracle."""
+    L, pos, vel, m = _clustered(L=21.0, n=9000, seed=11)
+    poly = gridfit.poly_coeffs()
+    dt = 0.02
+    before = ctx.get_tuning()
+    pmh = sr.PM(ctx, 16, L)
+    try:
+        ctx.set_tuning(xsplit=xsplit)
+        box, st = _state(sr, ctx, L, pos, vel, m)
+        gp, gv = _run(sr, ctx, pmh, box, st,
+                      sr.StepParams.make(R_MAX, EPS, poly, CELL, dt, 1, ml=(4, 1, 3)))
+    finally:
+        ctx.set_tuning(**before)
+        pmh.close()
+    P, V, _, _ = PMO.ksk_step(pos, vel.astype(np.float64), m.astype(np.float64), L, 16, R_MAX,
+                              EPS, poly.astype(np.float64), dt, 1, ml=(4, 1, 3, CELL))
+    dx = gp - P
+    dx -= L * np.round(dx / L)
+    vs = np.sqrt((V ** 2).sum(1).mean())
+    dv = np.abs(gv - V).max()
+    print("xsplit %d: max|dv| %.3e (rms v %.3e) max|dx| %.3e" % (xsplit, dv, vs, np.abs(dx).max()))
+    assert dv <= 2e-5 * vs + 1e-5
+    assert np.abs(dx).max() <= 2e-5 * dt * vs + 1e-6
+
+
 @pytest.mark.parametrize("n,seed", [(20000, 7), (60000, 8)])
 def test_multilevel_dense_cells_match_oracle(sr, ctx, n, seed):
     """Dense cells whose stencils hold 4,096..19,329 sources: the multilevel
