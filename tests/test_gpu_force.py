@@ -139,7 +139,7 @@ def test_dense_cells_cut_into_sub_items(sr, ctx, poly):
     sub-items over the stencil sources, whose partial sums are added in
     sub-item order.  The result is bitwise reproducible, the same under
     every item order and persistence setting, and within the oracle's bound
-    on targets drawn from the densest cells."""
+    on targets drawn from the densest cells, also on x sub-cells."""
     p = W.nfw_share(300_000, 40.0, 13)
     before = ctx.get_tuning()
     try:
@@ -147,6 +147,8 @@ def test_dense_cells_cut_into_sub_items(sr, ctx, poly):
         a1, _ = _gpu_force(sr, ctx, p, 3.0, poly)
         ctx.set_tuning(order=0, persistent=1)
         a2, _ = _gpu_force(sr, ctx, p, 3.0, poly)
+        ctx.set_tuning(order=1, persistent=0, xsplit=3)
+        a3, _ = _gpu_force(sr, ctx, p, 3.0, poly)  # stencils of 9 rows of 7 sub-cells
     finally:
         ctx.set_tuning(**before)
     assert np.array_equal(a0, a1) and np.array_equal(a0, a2)
@@ -156,8 +158,10 @@ def test_dense_cells_cut_into_sub_items(sr, ctx, poly):
     rng = np.random.default_rng(79)
     tg = np.unique(np.concatenate([rng.choice(p.n, 256, replace=False),
                                    rng.choice(dense, 256, replace=False)]))
-    st = check_accel(a0[tg], _ref(p, poly, targets=tg), "dense sub-items")
+    ref = _ref(p, poly, targets=tg)
+    st = check_accel(a0[tg], ref, "dense sub-items")
     print("dense sub-items", st)
+    print("dense sub-items, x sub-cells 3", check_accel(a3[tg], ref, "dense sub-items xsplit 3"))
 
 
 def test_determinism_and_momentum(sr, ctx, poly):
