@@ -98,8 +98,9 @@ int sr_set_stream(sr_ctx *ctx, void *hip_stream);
 int sr_arena_info(const sr_ctx *ctx, size_t *allocated, size_t *high_water);
 
 /* Wait for all work enqueued by this context; returns SR_ERANGE if a kernel
- * saw a coordinate outside [0, L) or a NaN since the last sr_sync (the
- * results of such calls are undefined but every access stayed in bounds),
+ * saw a coordinate outside [0, L) or a NaN, or sr_permute a perm entry
+ * outside [0, n), since the last sr_sync (the results of such calls are
+ * undefined but every access stayed in bounds),
  * SR_EDEVICE on a HIP error, else SR_OK.  Clears the device status. */
 int sr_sync(sr_ctx *ctx);
 
@@ -136,6 +137,21 @@ int sr_scratch_bytes(const sr_box *box, double cell, int64_t n, int with_force, 
  * n out of range), SR_ENOMEM; SR_ERANGE later from sr_sync. */
 int sr_bin(sr_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
            const sr_box *box, double cell, int32_t *cell_offsets, int32_t *perm);
+
+/* Out-of-place re-ordering of one particle attribute by a permutation, the
+ * attribute-at-a-time re-ordering that a permutation array allows (Sec. 2.7):
+ * out[k] = in[perm[k]] for 0 <= k < n.
+ *   perm       : device int32[n], a permutation of 0..n-1 (sr_bin's perm).
+ *   in, out    : device arrays of n elements of elem_bytes each (4, 8 or 16:
+ *                float or int32, double, float4); they must not overlap.
+ * With one scratch array of the largest attribute a caller re-orders all its
+ * attributes in turn.  Particles kept in the last binning's cell order make
+ * the next binning cheaper (few distinct cells per block of the histogram).
+ * Errors: SR_EINVAL synchronously (n < 0 or > 2^31 - 1, NULL pointer with
+ * n > 0, another elem_bytes, in == out); a perm entry outside [0, n) writes
+ * zero bytes to its slot and makes sr_sync return SR_ERANGE. */
+int sr_permute(sr_ctx *ctx, const int32_t *perm, int64_t n, int32_t elem_bytes, const void *in,
+               void *out);
 
 /* Short-range accelerations (Eq. (force), Sec. 3.1) of all n particles.
  *   x, y, z, mass : device float32[n] (mass may be any finite values).

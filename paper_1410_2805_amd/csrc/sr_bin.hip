@@ -996,6 +996,25 @@ __global__ __launch_bounds__(kBlock) void k_key_offsets(const unsigned *__restri
     offsets[c] = lo;
 }
 
+// out[k] = in[perm[k]]; an entry outside [0, n) sets the status word and
+// writes zero bytes.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute(const int *__restrict__ perm, int n,
+                                                    const T *__restrict__ in, T *__restrict__ out,
+                                                    int *__restrict__ status)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n)
+        return;
+    const unsigned p = (unsigned)perm[k];
+    if (p >= (unsigned)n) {
+        atomicOr(status, 1);
+        out[k] = T{};
+        return;
+    }
+    out[k] = in[p];
+}
+
 inline unsigned blocks_for(int64_t n, int per)
 {
     return (unsigned)((n + per - 1) / per);
@@ -1257,4 +1276,39 @@ extern "C" int sr_bin(sr_ctx *ctx, const float *x, const float *y, const float *
     Bump b{ctx->arena, 0, ctx->arena_cap};
     bin_layout(b, n, B.ctot, 1, s);
     return bin_enqueue(ctx, B, s, cell_offsets, perm, nullptr, nullptr, nullptr);
+}
+
+extern "C" int sr_permute(sr_ctx *ctx, const int32_t *perm, int64_t n, int32_t elem_bytes,
+                          const void *in, void *out)
+{
+    if (!ctx)
+        return SR_EINVAL;
+    ctx->err.clear();
+    if (n < 0 || n > INT_MAX)
+        return sr_fail(ctx, SR_EINVAL, "n=%lld out of range", (long long)n);
+    if (elem_bytes != 4 && elem_bytes != 8 && elem_bytes != 16)
+        return sr_fail(ctx, SR_EINVAL, "elem_bytes must be 4, 8 or 16 (got %d)", elem_bytes);
+    if (n == 0)
+        return SR_OK;
+    if (!perm || !in || !out)
+        return sr_fail(ctx, SR_EINVAL, "NULL pointer");
+    if (in == out)
+        return sr_fail(ctx, SR_EINVAL, "in and out must be different arrays");
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return sr_fail(ctx, SR_EDEVICE, "hipSetDevice failed");
+    const int ni = (int)n;
+    const dim3 grid(blocks_for(n, kBlock)), block(kBlock);
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_permute<unsigned>, grid, block, 0, ctx->stream, perm, ni,
+                           static_cast<const unsigned *>(in), static_cast<unsigned *>(out),
+                           ctx->status);
+    else if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_permute<unsigned long long>, grid, block, 0, ctx->stream, perm, ni,
+                           static_cast<const unsigned long long *>(in),
+                           static_cast<unsigned long long *>(out), ctx->status);
+    else
+        hipLaunchKernelGGL(k_permute<uint4>, grid, block, 0, ctx->stream, perm, ni,
+                           static_cast<const uint4 *>(in), static_cast<uint4 *>(out),
+                           ctx->status);
+    return sr_check_launch(ctx, "k_permute");
 }

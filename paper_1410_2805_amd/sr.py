@@ -160,6 +160,7 @@ def _load():
         "sr_timing_collect": (ctypes.c_int, [P, ctypes.POINTER(f64), ctypes.POINTER(f64),
                                              ctypes.POINTER(i64)]),
         "sr_kinetic": (ctypes.c_int, [P, P, P, P, P, i64, P]),
+        "sr_permute": (ctypes.c_int, [P, P, i64, i32, P, P]),
         "sr_force_tree": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, f32, f32, P, i32, P, P, P,
                                          P]),
         "sr_tree_leaves": (ctypes.c_int, [P, P, P, P, P, i64, BP, f64, i32, P,
@@ -195,7 +196,8 @@ def exported_symbols() -> list[str]:
             "sr_server_cancel", "sr_server_info_get", "sr_server_destroy",
             "sr_pm_create", "sr_pm_destroy", "sr_pm_bytes", "sr_pm_deposit", "sr_pm_fft",
             "sr_pm_force", "sr_pm_force_split", "sr_ksk_step", "sr_force_tree",
-            "sr_tree_leaves", "sr_kinetic", "sr_force_static", "sr_force_static_capacity"]
+            "sr_tree_leaves", "sr_kinetic", "sr_force_static", "sr_force_static_capacity",
+            "sr_permute"]
 
 
 def _ptr(t):
@@ -314,6 +316,25 @@ def sr_bin(ctx: Context, x, y, z, box: Box, cell: float, cell_offsets=None, perm
     ctx._check(lib.sr_bin(ctx._h, _f32(x, n, "x"), _f32(y, n, "y"), _f32(z, n, "z"), n,
                           ctypes.byref(box), float(cell), _ptr(cell_offsets), _ptr(perm)))
     return cell_offsets, perm
+
+
+def sr_permute(ctx: Context, perm, a, out=None):
+    """out[k] = a[perm[k]] (a contiguous 1-D CUDA tensor of 4-, 8- or 16-byte
+    elements; perm int32); returns out."""
+    n = int(perm.shape[0])
+    if not (isinstance(perm, torch.Tensor) and perm.is_cuda and perm.dtype == torch.int32
+            and perm.is_contiguous() and perm.dim() == 1):
+        raise ValueError("perm must be a contiguous 1-D int32 CUDA tensor")
+    if not (isinstance(a, torch.Tensor) and a.is_cuda and a.is_contiguous() and a.dim() == 1
+            and a.shape[0] == n):
+        raise ValueError("a must be a contiguous 1-D CUDA tensor of length %d" % n)
+    if out is None:
+        out = torch.empty_like(a)
+    if not (out.dtype == a.dtype and out.is_cuda and out.is_contiguous() and out.shape == a.shape):
+        raise ValueError("out must match a")
+    ctx._bind_stream()
+    ctx._check(lib.sr_permute(ctx._h, _ptr(perm), n, a.element_size(), _ptr(a), _ptr(out)))
+    return out
 
 
 def sr_force(ctx: Context, x, y, z, m, box: Box, cell: float, r_max: float, eps: float, poly,

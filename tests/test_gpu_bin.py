@@ -155,6 +155,48 @@ def test_radix_path(sr, ctx, case):
     _assert_same(*_bin_both(sr, ctx, x, y, z, L, 3.0))
 
 
+def test_permute_keeps_cell_order(sr, ctx):
+    """sr_permute re-orders attributes by sr_bin's permutation (4-, 8- and
+    16-byte elements against numpy's fancy indexing); binning the re-ordered
+    particles again gives the same offsets and the identity permutation."""
+    rng = np.random.default_rng(21)
+    n = 50_000
+    x, y, z = (rng.random(n, dtype=np.float32) * np.float32(29.9) for _ in range(3))
+    dev = "cuda:0"
+    tx, ty, tz = (torch.from_numpy(v).to(dev) for v in (x, y, z))
+    box = sr.Box.make(30.0)
+    off, perm = sr.sr_bin(ctx, tx, ty, tz, box, 3.0)
+    ids = torch.arange(n, dtype=torch.int32, device=dev) * 7
+    d64 = torch.from_numpy(rng.random(n)).to(dev)
+    c128 = torch.from_numpy(rng.random(n) + 1j * rng.random(n)).to(dev)
+    outs = [sr.sr_permute(ctx, perm, t) for t in (tx, ty, tz, ids, d64, c128)]
+    ctx.sync()
+    p = perm.cpu().numpy()
+    for t, o in zip((tx, ty, tz, ids, d64, c128), outs):
+        assert np.array_equal(o.cpu().numpy(), t.cpu().numpy()[p])
+    off2, perm2 = sr.sr_bin(ctx, outs[0], outs[1], outs[2], box, 3.0)
+    ctx.sync()
+    assert np.array_equal(off2.cpu().numpy(), off.cpu().numpy())
+    assert np.array_equal(perm2.cpu().numpy(), np.arange(n, dtype=np.int32))
+
+
+def test_permute_errors(sr, ctx):
+    dev = "cuda:0"
+    a = torch.arange(8, dtype=torch.float32, device=dev)
+    bad = torch.tensor([0, 1, 2, 3, 4, 5, 6, 8], dtype=torch.int32, device=dev)
+    out = sr.sr_permute(ctx, bad, a)
+    with pytest.raises(sr.SRError) as e:
+        ctx.sync()
+    assert e.value.code == sr.SR_ERANGE
+    assert out[7].item() == 0.0 and out[:7].cpu().tolist() == list(range(7))
+    ctx.sync()  # status cleared
+    perm = torch.arange(8, dtype=torch.int32, device=dev)
+    with pytest.raises(sr.SRError):
+        sr.sr_permute(ctx, perm, a, out=a)  # in place is refused
+    with pytest.raises(sr.SRError):
+        sr.sr_permute(ctx, perm, torch.zeros(8, dtype=torch.int16, device=dev))  # 2-byte elements
+
+
 def test_invalid_args(sr, ctx):
     t = torch.zeros(4, device="cuda:0")
     with pytest.raises(sr.SRError):
