@@ -250,8 +250,11 @@ __global__ __launch_bounds__(256) void k_subsum(Batch B, const int4 *__restrict_
     }
 }
 
-// Persistent variant: a fixed grid of workgroups takes items in order from a
-// counter until none are left (every workgroup reaches the exit).
+// Persistent variant: a fixed grid of workgroups takes kPersistentGrab
+// consecutive items at a time from a counter until none are left (every
+// workgroup reaches the exit).  Taking two per atomic halves the traffic on
+// the one counter address, which bounded the pass on many-item batches.
+constexpr int kPersistentGrab = 2;
 __global__ __launch_bounds__(64) void k_force_persistent(Batch B, const int4 *__restrict__ items,
                                                          const int *__restrict__ n_items,
                                                          const float4 *__restrict__ sorted,
@@ -267,14 +270,16 @@ __global__ __launch_bounds__(64) void k_force_persistent(Batch B, const int4 *__
     const int n = *n_items;
     for (;;) {
         if (threadIdx.x == 0)
-            next = atomicAdd(queue, 1);
+            next = atomicAdd(queue, kPersistentGrab);
         __syncthreads();
-        const int pos = next;
+        const int p0 = next;
         __syncthreads();
-        if (pos >= n)
+        if (p0 >= n)
             break;
-        process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st,
-                     threadIdx.x, subsums);
+        const int pe = p0 + kPersistentGrab < n ? p0 + kPersistentGrab : n;
+        for (int pos = p0; pos < pe; ++pos)
+            process_item(B, items[pos], sorted, offsets, perm, mass_mixed, fp, tile, st,
+                         threadIdx.x, subsums);
     }
 }
 
